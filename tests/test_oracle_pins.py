@@ -1,0 +1,339 @@
+"""Pins of the oracle's verdicts and coefficients against facts the paper and
+the mathematics fix (CPU only)."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact
+from tests import _ref
+
+CUBE = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0],
+                 [0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1]], dtype=np.float64)
+MIDDLE_LAYER = [12, 13, 14, 15, 21, 22, 23, 24, 26]   # 0-based Fig. 3 indices with zeta = 1/2
+
+
+def _one(P, max_depth=6):
+    r = oracle.check(np.asarray(P)[None], max_depth=max_depth, details=True)
+    return {k: (v[0] if len(v) else None) for k, v in r.items() if k != "fragile"}
+
+
+# ---------------------------------------------------------------- figures 5-7
+
+def test_fig5_invalid_with_all_27_samples_positive():
+    P, expect = _ref.read_figure("fig5.txt")
+    assert expect["verdict"] == ["INVALID"]
+    r = _one(P)
+    assert r["verdict"] == oracle.INVALID
+    b, c = oracle.coefficients(P[None], samples=True)
+    assert (c[0] > 0).all()                       # Section 7: J > 0 at all 27 nodes
+    assert r["level"] > 0                          # found by subdivision only
+    # the witness is a point where J <= 0 (independent evaluator, exact)
+    w = [Fraction(float(x)) for x in r["witness"]]
+    Pf = [tuple(Fraction(float(x)) for x in p) for p in P]
+    assert _ref.jacobian_shape(Pf, *w) <= 0
+    assert exact.validity(P)["verdict"] == exact.INVALID
+
+
+def test_fig6_valid_with_negative_coefficients():
+    P, expect = _ref.read_figure("fig6.txt")
+    assert expect["verdict"] == ["VALID"]
+    r = _one(P)
+    assert r["verdict"] == oracle.VALID
+    b = oracle.coefficients(P[None])[0]
+    assert b.min() < 0                              # certified only after subdivision
+    assert r["level"] >= 1
+    # dense sampling agrees with validity
+    assert _ref.jacobian_grid(P, 40).min() > 0
+
+
+def test_fig7_invalid_with_good_corner_quality():
+    P, expect = _ref.read_figure("fig7.txt")
+    assert expect["verdict"] == ["INVALID"]
+    assert _one(P)["verdict"] == oracle.INVALID
+    # minimum scaled Jacobian over the 8 corners, Section 7: printed 0.64
+    lo, hi = (float(x) for x in expect["corner_scaled_jacobian_min"])
+    nbr = {0: (1, 3, 4), 1: (2, 0, 5), 2: (3, 1, 6), 3: (0, 2, 7),
+           4: (7, 5, 0), 5: (4, 6, 1), 6: (5, 7, 2), 7: (6, 4, 3)}
+    q = []
+    for k, (i, j, l) in nbr.items():
+        e = [P[i] - P[k], P[j] - P[k], P[l] - P[k]]
+        q.append(np.linalg.det(np.array(e).T) / np.prod([np.linalg.norm(v) for v in e]))
+    assert lo <= min(q) < hi
+
+
+# -------------------------------------------------------------- closed forms
+
+def test_unit_cube_all_coefficients_one():
+    b = oracle.coefficients(CUBE[None])[0]
+    assert (b == 1.0).all()
+    assert _one(CUBE)["verdict"] == oracle.VALID
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_parallelepiped_constant_coefficients(seed):
+    rng = np.random.default_rng(seed)
+    A = np.eye(3) + rng.integers(-8, 9, size=(3, 3)) / 16.0
+    t = rng.integers(-100, 101, size=3) / 4.0
+    P = CUBE @ A.T + t
+    b, _ = exact.coefficients(P)
+    detA = exact.det3(*[tuple(Fraction(float(A[i, j])) for i in range(3)) for j in range(3)])
+    assert all(x == detA for x in b)
+    bo = oracle.coefficients(P[None])[0]
+    assert np.allclose(bo, float(detA), rtol=1e-14, atol=0)
+    assert _one(P)["verdict"] == (oracle.VALID if detA > 0 else oracle.INVALID)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_corner_coefficients_are_corner_jacobians(seed):
+    rng = np.random.default_rng(seed)
+    P = CUBE + rng.uniform(-0.4, 0.4, size=(8, 3))
+    b = oracle.coefficients(P[None])[0]
+    for k in range(8):
+        node = _ref.NODES[k]
+        assert b[k] == oracle.jacobian(P, *(x / 2 for x in node))
+
+
+def _twisted(theta_deg):
+    th = math.radians(theta_deg)
+    c, s = math.cos(th), math.sin(th)
+    if theta_deg == 90:
+        c, s = 0.0, 1.0
+    if theta_deg == 180:
+        c, s = -1.0, 0.0
+    P = CUBE.copy()
+    for k in range(4, 8):
+        x, y = P[k, 0] - 0.5, P[k, 1] - 0.5
+        P[k, 0] = 0.5 + c * x - s * y
+        P[k, 1] = 0.5 + s * x + c * y
+    return P, c
+
+
+@pytest.mark.parametrize("theta,verdict,level", [
+    (30, oracle.VALID, 0), (89, oracle.VALID, 0), (90, oracle.VALID, 1),
+    (120, oracle.VALID, 1), (179, oracle.VALID, 1), (180, oracle.INVALID, 0)])
+def test_twisted_cube(theta, verdict, level):
+    # J = (1-zeta)^2 + 2 zeta (1-zeta) cos(theta) + zeta^2: coefficients
+    # cos(theta) on the middle layer, 1 elsewhere; min J = cos^2(theta/2).
+    P, c = _twisted(theta)
+    b = oracle.coefficients(P[None])[0]
+    expect = np.ones(27)
+    expect[MIDDLE_LAYER] = c
+    assert np.allclose(b, expect, rtol=0, atol=1e-14)
+    r = _one(P)
+    assert (r["verdict"], r["level"]) == (verdict, level)
+    g = _ref.jacobian_grid(P, 32).min()
+    assert abs(g - math.cos(math.radians(theta) / 2) ** 2) < 1e-12
+
+
+def _prism(eps):
+    """Unit square at zeta=0, top = R applied about the centre with
+    det((1-z)I + zR) = 1 + t z + d z^2, min eps at z* = 1/3 (exact for dyadic eps)."""
+    d = 9.0 * (1.0 - eps)
+    t = -6.0 * (1.0 - eps)
+    R = np.array([[1 + t / 2, 1.0], [t * t / 4 - d, 1 + t / 2]])
+    P = CUBE.copy()
+    for k in range(4, 8):
+        v = R @ (P[k, :2] - 0.5)
+        P[k, :2] = 0.5 + v
+    return P, t, d
+
+
+def _prism_1d(t, d, max_depth):
+    """Reference: J depends on zeta only, so the 3D algorithm reduces to 1D
+    Bernstein subdivision of f(z) = 1 + t z + d z^2 (textbook formula for the
+    coefficients of a quadratic on [a, b]).  Returns (verdict, level)."""
+    t, d = Fraction(t), Fraction(d)
+
+    def f(z):
+        return 1 + t * z + d * z * z
+
+    def coeffs(a, b):
+        return f(a), f(a) + (b - a) * (t + 2 * d * a) / 2, f(b)
+
+    # step 2: values at zeta = 0, 1/2, 1 (corners and edge midpoints)
+    if min(f(Fraction(0)), f(Fraction(1, 2)), f(Fraction(1))) <= 0:
+        return oracle.INVALID, 0
+    if min(coeffs(Fraction(0), Fraction(1))) > 0:
+        return oracle.VALID, 0
+    live, undecided, deepest = [(Fraction(0), Fraction(1))], False, 0
+    for level in range(1, max_depth + 1):
+        nxt = []
+        for a, b in live:
+            for lo, hi in ((a, (a + b) / 2), ((a + b) / 2, b)):
+                deepest = level
+                c0, c1, c2 = coeffs(lo, hi)
+                if min(c0, c2) <= 0:
+                    return oracle.INVALID, level
+                if min(c0, c1, c2) > 0:
+                    continue
+                if level < max_depth:
+                    nxt.append((lo, hi))
+                else:
+                    undecided = True
+        live = nxt
+        if not live:
+            break
+    return (oracle.UNDECIDED if undecided else oracle.VALID), deepest
+
+
+@pytest.mark.parametrize("eps,max_depth", [
+    (0.25, 6), (2.0 ** -6, 6), (2.0 ** -10, 6), (2.0 ** -20, 6), (-(2.0 ** -10), 6),
+    (-(2.0 ** -20), 6), (0.0, 6), (0.0, 3), (2.0 ** -20, 11), (-(2.0 ** -20), 11)])
+def test_sheared_prism_against_1d_reduction(eps, max_depth):
+    P, t, d = _prism(eps)
+    b, _ = exact.coefficients(P)
+    layer = {0: 1, 1: 1 + t / 2, 2: 1 + t + d}
+    for a, node in enumerate(_ref.NODES):
+        assert b[a] == Fraction(layer[node[2]])
+    expect = _prism_1d(t, d, max_depth)
+    r = _one(P, max_depth)
+    assert r["verdict"] == expect[0]
+    if expect[0] == oracle.INVALID:
+        # the order of exploration may differ (depth-first here, level by level
+        # in the reference); the witness must be a point with f(zeta) <= 0
+        z = Fraction(float(r["witness"][2]))
+        assert 1 + Fraction(t) * z + Fraction(d) * z * z <= 0
+    else:
+        assert r["level"] == expect[1]
+
+
+# ---------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("seed", range(3))
+def test_cube_symmetries_permute_coefficients(seed):
+    rng = np.random.default_rng(100 + seed)
+    P = CUBE + rng.integers(-5, 6, size=(8, 3)) / 16.0
+    b, _ = exact.coefficients(P)
+    v0 = oracle.check(P[None])["verdict"][0]
+    for sym in _ref.cube_symmetries():
+        Q, amap = _ref.apply_symmetry(P, sym)
+        bq, _ = exact.coefficients(Q)
+        assert bq == [sym[2] * b[amap[a]] for a in range(27)]
+        v = oracle.check(Q[None])["verdict"][0]
+        if sym[2] > 0:
+            assert v == v0
+        elif v0 == oracle.VALID:
+            assert v == oracle.INVALID
+
+
+def test_affine_map_scales_coefficients():
+    rng = np.random.default_rng(11)
+    P = CUBE + rng.integers(-6, 7, size=(8, 3)) / 32.0
+    A = np.array([[2.0, 0.5, 0.0], [0.25, 1.0, -0.5], [0.0, 0.75, 1.5]])
+    t = np.array([3.0, -7.25, 100.5])
+    b, _ = exact.coefficients(P)
+    b2, _ = exact.coefficients(P @ A.T + t)
+    detA = exact.det3(*[tuple(Fraction(float(A[i, j])) for i in range(3)) for j in range(3)])
+    assert b2 == [detA * x for x in b]
+
+
+# ---------------------------------------------------- bounds and brute force
+
+@pytest.mark.parametrize("seed", range(3))
+def test_convex_hull_bounds_against_dense_sampling(seed):
+    rng = np.random.default_rng(seed)
+    Ps = CUBE[None] + rng.uniform(-0.45, 0.45, size=(40, 8, 3))
+    b = oracle.coefficients(Ps)
+    for P, bb in zip(Ps, b):
+        g = _ref.jacobian_grid(P, 24).min()
+        assert bb.min() <= g + 1e-12
+        assert g <= bb[:8].min() + 1e-12
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_brute_force_on_tangled_hexes(seed):
+    # Strong noise: many tangled elements.  VALID => J > 0 on a dense grid;
+    # a negative grid value => not VALID; INVALID => an exact witness J <= 0.
+    rng = np.random.default_rng(seed)
+    Ps = CUBE[None] + rng.uniform(-0.6, 0.6, size=(60, 8, 3))
+    r = oracle.check(Ps, details=True)
+    seen = set()
+    for P, v, w in zip(Ps, r["verdict"], r["witness"]):
+        g = _ref.jacobian_grid(P, 20).min()
+        seen.add(int(v))
+        if v == oracle.VALID:
+            assert g > 0
+        if g <= 0:
+            assert v != oracle.VALID
+        if v == oracle.INVALID:
+            Pf = [tuple(Fraction(float(x)) for x in p) for p in P]
+            assert _ref.jacobian_shape(Pf, *[Fraction(float(x)) for x in w]) <= 0
+    assert {oracle.VALID, oracle.INVALID} <= seen
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_integer_lattice_fp64_equals_exact(seed):
+    # Small-integer coordinates: every FP64 operation of the oracle is exact,
+    # so its coefficients and verdicts must equal the rational computation,
+    # including degenerate elements (coincident nodes give J = 0 -> INVALID).
+    rng = np.random.default_rng(seed)
+    Ps = (CUBE[None] * 4 + rng.integers(-2, 3, size=(60, 8, 3))).astype(np.float64)
+    Ps[:10, 1] = Ps[:10, 0]           # coincident nodes
+    b = oracle.coefficients(Ps)
+    r = oracle.check(Ps, details=True)
+    for P, bb, v in zip(Ps, b, r["verdict"]):
+        e = exact.validity(P)
+        be, _ = exact.coefficients(P)
+        assert [Fraction(float(x)) for x in bb] == be
+        assert v == e["verdict"]
+    assert (r["verdict"][:10] == oracle.INVALID).all()
+
+
+def test_exact_tier_decides_fragile_elements():
+    # Values exactly zero are inside every FP64 bound: the C pass reports
+    # FRAGILE and the exact tier decides.  Twisted cube at 180 degrees: J = 0
+    # on the middle plane (edge midpoints 13-16) -> INVALID at step 2.
+    P, _ = _twisted(180)
+    r = oracle.check(P[None], settle_fragile=False)
+    assert r["verdict"][0] == oracle.FRAGILE
+    assert oracle.check(P[None])["verdict"][0] == oracle.INVALID
+    # At 90 degrees the middle-layer coefficients are exactly 0: with no
+    # subdivision allowed the root is capped -> exact tier says UNDECIDED.
+    P, _ = _twisted(90)
+    r = oracle.check(P[None], max_depth=0, settle_fragile=False)
+    assert r["verdict"][0] == oracle.FRAGILE
+    assert oracle.check(P[None], max_depth=0)["verdict"][0] == oracle.UNDECIDED
+    assert oracle.check(P[None], max_depth=1)["verdict"][0] == oracle.VALID
+
+
+def test_degenerate_point_element():
+    P = np.zeros((8, 3))
+    assert oracle.check(P[None])["verdict"][0] == oracle.INVALID
+
+
+def test_bad_input():
+    P = CUBE.copy()
+    P[3, 1] = np.nan
+    Q = CUBE.copy()
+    Q[6, 2] = np.inf
+    r = oracle.check(np.stack([P, Q]))
+    assert (r["verdict"] == oracle.BAD_INPUT).all()
+    assert np.isnan(r["min_coeff"]).all()
+
+
+@pytest.mark.parametrize("kind", ["random", "offset", "flat", "scaled"])
+def test_error_bounds_hold_against_exact(kind):
+    """Observed |b^ - b| and |c^ - c| stay below the oracle's certified bounds."""
+    rng = np.random.default_rng({"random": 1, "offset": 2, "flat": 3, "scaled": 4}[kind])
+    n = 60
+    Ps = CUBE[None] + rng.uniform(-0.4, 0.4, size=(n, 8, 3))
+    if kind == "offset":
+        Ps = Ps + rng.uniform(100, 1000, size=(n, 1, 3))
+    if kind == "flat":
+        Ps[:, :, 2] *= 1e-9
+    if kind == "scaled":
+        Ps = Ps * 10.0 ** rng.uniform(-3, 3, size=(n, 1, 1))
+    bf, cf = oracle.coefficients(Ps, samples=True)
+    M = oracle.scale(Ps)
+    k = oracle.bound_constants()
+    worst_b = worst_c = 0.0
+    for P, bb, cc, m in zip(Ps, bf, cf, M):
+        be, ce = exact.coefficients(P)
+        eb = max(abs(Fraction(float(x)) - y) for x, y in zip(bb, be))
+        ec = max(abs(Fraction(float(x)) - y) for x, y in zip(cc, ce))
+        worst_b = max(worst_b, float(eb) / (k["tau_b"] * k["u"] * m))
+        worst_c = max(worst_c, float(ec) / (k["tau_c"] * k["u"] * m))
+    assert worst_b < 1.0 and worst_c < 1.0
