@@ -1,0 +1,203 @@
+/*
+ * hexval.h: C ABI of libhexval, a validity test for linear hexahedra on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: A. Johnen, J.-C. Weill, J.-F. Remacle, "Robust and efficient
+ * validation of the linear hexahedral element", IMR 2017.  For each element
+ * the 8 corner points (Appendix A order: (0,0,0) (1,0,0) (1,1,0) (0,1,0)
+ * (0,0,1) (1,0,1) (1,1,1) (0,1,1) of the reference cube [0,1]^3) give the 20
+ * values of the Jacobian determinant at the corners and edge midpoints as
+ * triple products (Section 5); the fixed 27x20 matrix of Table 3 maps them to
+ * the 27 Bezier coefficients of the triquadratic determinant (Sections 3-4);
+ * the algorithm of Section 6 then decides: a non-positive value -> INVALID,
+ * all coefficients b_9..b_27 positive -> VALID, otherwise the element is
+ * subdivided adaptively.
+ *
+ * Semantics fixed by this library (where the paper is silent):
+ *   - validity is strict positivity of J on [0,1]^3: a value <= 0 is invalid,
+ *     only values > 0 certify;
+ *   - subdivision stops at a depth cap (default 6): an element with an
+ *     ambiguous sub-box at the cap and no non-positive value found is
+ *     UNDECIDED;
+ *   - verdicts are those of the algorithm in EXACT arithmetic: every FP64
+ *     (or FP32) sign decision is checked against a rigorous error bound and
+ *     the few elements whose decisions cannot be certified are recomputed
+ *     exactly on the host;
+ *   - min_coeff is the minimum of the 27 top-level coefficients (a lower
+ *     bound of min J by the convex-hull property of Section 3.1), NaN for
+ *     BAD_INPUT.
+ *
+ * Conventions for every entry point:
+ *   - array pointers named "device" are device pointers (hipMalloc'd memory or
+ *     ROCm torch tensors) on the current HIP device; the caller owns all
+ *     buffers it passes and the library never frees them;
+ *   - status codes are returned, nothing is thrown across the ABI; the message
+ *     of the last non-OK status of the calling thread is hexval_last_error();
+ *   - n == 0 is a no-op returning HEXVAL_OK; a NULL required pointer with
+ *     n > 0, n < 0 or an option out of range returns HEXVAL_E_ARG without
+ *     touching the GPU;
+ *   - per-element input problems never fail a call: the element gets verdict
+ *     HEXVAL_BAD_INPUT.
+ */
+#ifndef HEXVAL_H
+#define HEXVAL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Per-element verdicts (uint8). */
+enum {
+    HEXVAL_INVALID = 0,   /* J <= 0 somewhere on [0,1]^3 (a value <= 0 was found) */
+    HEXVAL_VALID = 1,     /* J > 0 on [0,1]^3 (all coefficients of a cover positive) */
+    HEXVAL_UNDECIDED = 2, /* depth cap reached with no non-positive value found */
+    HEXVAL_BAD_INPUT = 3  /* non-finite coordinate, or index out of range when validated */
+};
+
+/* Status codes. */
+enum {
+    HEXVAL_OK = 0,
+    HEXVAL_E_ARG = 1,   /* invalid argument (see conventions) */
+    HEXVAL_E_HIP = 2,   /* HIP runtime error, no usable gfx950 device, or kernel failure */
+    HEXVAL_E_NOMEM = 3, /* device or host allocation failed */
+    HEXVAL_E_QUEUE = 4, /* the subdivision queue could not make progress */
+    HEXVAL_E_BUSY = 5   /* server: no capacity for this request (never returned by submit) */
+};
+
+/* Precision of the first pass. */
+enum {
+    HEXVAL_FP64 = 0,        /* every element in FP64 */
+    HEXVAL_FP32_FILTER = 1  /* FP32 pass with a forward error bound per value and
+                               coefficient; elements it cannot certify, and every
+                               subdivision, are recomputed in FP64 */
+};
+
+/* A mesh.  points: device, [n_points,3] float64 when connectivity != NULL,
+ * else [n,8,3] float64 (8 points per element, Appendix A order).
+ * connectivity: device, [n,8] int32 vertex ids (Appendix A order) or NULL.
+ * n_points: number of vertices; used only to validate indices. */
+typedef struct {
+    const double* points;
+    int64_t n_points;
+    const int32_t* connectivity;
+    int64_t n;
+} hexval_mesh_t;
+
+/* Counters and device timings of one call (filled when opts->stats != NULL). */
+typedef struct {
+    int64_t n_elements;    /* elements checked */
+    int64_t n_subdivided;  /* elements sent to subdivision */
+    int64_t n_nodes;       /* sub-boxes evaluated by the subdivision kernel */
+    int64_t n_exact;       /* elements settled by the exact tier */
+    int64_t n_recheck;     /* FP32_FILTER: elements recomputed in FP64 */
+    int64_t n_rounds;      /* passes (more than 1 only after queue overflow) */
+    int32_t max_level;     /* deepest sub-box level evaluated */
+    int32_t timing;        /* IN: nonzero -> record the device times below */
+    float ms_first_pass;   /* device time of the first-pass kernel (FP64 or FP32) */
+    float ms_recheck;      /* device time of the FP64 recheck kernel (FP32_FILTER) */
+    float ms_subdivision;  /* device time of subdivision drain + verdict fold */
+    float ms_total;        /* device time from first launch to last kernel */
+} hexval_stats_t;
+
+/* Options.  Use hexval_opts_default() and change fields. */
+typedef struct {
+    int32_t precision;        /* HEXVAL_FP64 (default) or HEXVAL_FP32_FILTER */
+    int32_t max_depth;        /* subdivision depth cap, 0..20, default 6 */
+    int32_t validate_indices; /* nonzero: connectivity entries outside [0,n_points)
+                                 give BAD_INPUT (default 0: indices are trusted) */
+    int32_t block_threads;    /* first-pass block size: 0 = tuned, else 64..1024,
+                                 a multiple of 64 */
+    int64_t queue_capacity;   /* subdivision queue nodes, 0 = automatic */
+    int64_t grid_blocks;      /* first-pass grid: 0 = tuned, else blocks */
+    void* stream;             /* hipStream_t to run on; NULL = the null stream */
+    hexval_stats_t* stats;    /* optional output */
+} hexval_opts_t;
+
+/* Fills *opts with the defaults above. */
+void hexval_opts_default(hexval_opts_t* opts);
+
+/*
+ * hexval_check: the Section 6 algorithm for n elements, FP64, default options,
+ * on the null stream; returns when the outputs are final.
+ * points: device [n,8,3] float64 when connectivity is NULL, else the vertex
+ *   array [*,3] float64 indexed by connectivity (device [n,8] int32; indices
+ *   are trusted).
+ * verdicts: device [n] uint8 (HEXVAL_INVALID .. HEXVAL_BAD_INPUT).
+ * min_coeffs: device [n] float64, or NULL.
+ */
+int hexval_check(const double* points, const int32_t* connectivity, int64_t n,
+                 uint8_t* verdicts, double* min_coeffs);
+
+/*
+ * hexval_check_ex: as hexval_check with options (precision, depth cap, index
+ * validation, stream, tuning, statistics).  Work is enqueued on opts->stream
+ * (NULL opts = defaults); the call returns when the outputs are final.
+ */
+int hexval_check_ex(const hexval_mesh_t* mesh, const hexval_opts_t* opts,
+                    uint8_t* verdicts, double* min_coeffs);
+
+/*
+ * hexval_check_batched: n_meshes independent meshes of different sizes in one
+ * persistent launch (elements of all meshes share the grid and one
+ * subdivision queue).  meshes: host array [n_meshes]; verdicts and min_coeffs:
+ * host arrays [n_meshes] of device pointers (min_coeffs may be NULL, or hold
+ * NULL entries).  Results equal those of hexval_check_ex on each mesh alone.
+ */
+int hexval_check_batched(const hexval_mesh_t* meshes, int32_t n_meshes,
+                         const hexval_opts_t* opts, uint8_t* const* verdicts,
+                         double* const* min_coeffs);
+
+/*
+ * hexval_coefficients: the 27 top-level Bezier coefficients of every element
+ * (Table 3 applied to the 20 triple-product values, FP64), Fig. 3 order.
+ * coeffs: device [n,27] float64.  stream: hipStream_t or NULL.  Returns after
+ * the kernel has completed.
+ */
+int hexval_coefficients(const hexval_mesh_t* mesh, void* stream, double* coeffs);
+
+/* ---- request queue with continuous batching --------------------------------
+ * A server runs a scheduler thread that admits submitted requests while fewer
+ * than max_slots are in flight and their device footprint fits the HBM budget,
+ * and runs admitted requests concurrently on separate HIP streams.  A request
+ * whose mesh pointers are device pointers references that memory (the caller
+ * keeps it alive until the request is done); with host_points/host_conn set
+ * the server copies the mesh to the device itself (pinned staging, copy
+ * stream) and counts that copy in the footprint. */
+typedef struct hexval_server hexval_server_t;
+
+typedef struct {
+    hexval_mesh_t mesh;        /* device mesh, or sizes only when host_* are set */
+    const double* host_points; /* optional host copy of mesh.points */
+    const int32_t* host_conn;  /* optional host copy of mesh.connectivity */
+    uint8_t* verdicts;         /* device [n] */
+    double* min_coeffs;        /* device [n] or NULL */
+} hexval_request_t;
+
+/* opts: precision, max_depth, validate_indices apply to every request (stream and
+ * stats are ignored).  hbm_budget_bytes: device memory the server may hold for
+ * requests in flight (queues + uploaded meshes), > 0.  max_slots: 1..64. */
+int hexval_server_create(const hexval_opts_t* opts, int64_t hbm_budget_bytes, int32_t max_slots,
+                         hexval_server_t** server);
+/* Never blocks on the GPU.  *ticket identifies the request.  Returns
+ * HEXVAL_E_BUSY only if one request alone can never fit the budget. */
+int hexval_server_submit(hexval_server_t* server, const hexval_request_t* request,
+                         uint64_t* ticket);
+/* *done = 1 once the outputs of ticket are final; latency_ms (optional) =
+ * submit-to-completion wall time.  The status of the finished request is the
+ * return value once done. */
+int hexval_server_poll(hexval_server_t* server, uint64_t ticket, int* done, double* latency_ms);
+/* Blocks until ticket is done; returns its status. */
+int hexval_server_wait(hexval_server_t* server, uint64_t ticket, double* latency_ms);
+/* Waits for all requests, stops the scheduler, frees the server's memory. */
+int hexval_server_destroy(hexval_server_t* server);
+
+/* Message of the last non-OK status returned to the calling thread. */
+const char* hexval_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HEXVAL_H */

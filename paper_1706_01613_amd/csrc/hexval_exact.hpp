@@ -1,0 +1,9 @@
+// Exact tier (host): verdict of one element in integer arithmetic.
+#pragma once
+#include <stdint.h>
+
+namespace hexval {
+// pts: 8 points (Appendix A order) x 3 coordinates.  Returns 0 INVALID,
+// 1 VALID, 2 UNDECIDED, 3 BAD_INPUT (non-finite coordinate).
+uint8_t exact_verdict(const double pts[24], int max_depth);
+}

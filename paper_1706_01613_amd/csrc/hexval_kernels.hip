@@ -1,0 +1,502 @@
+// HIP kernels of the validity test for linear hexahedra (gfx950).
+//
+//   k_top_f64      first pass, one element per lane: gather the 8 corners,
+//                  20 triple products (Section 5), Table 3, certified
+//                  decisions of Section 6 steps 2 and 4; ambiguous elements
+//                  are compacted (ballot + one atomic per wave) into the
+//                  subdivision queue, uncertain ones into the exact list.
+//   k_drain        persistent drain of the subdivision queue: eight lanes per
+//                  node, one lane per child (de Casteljau at 1/2), children
+//                  that stay ambiguous are pushed back until the depth cap.
+//   k_fold         folds the per-element flags of subdivided elements into
+//                  verdicts (INVALID > exact > overflow > UNDECIDED > VALID).
+//   small kernels  counter reset, batched tile table, deferred-element
+//                  collection, exact-tier gather/scatter, coefficients.
+#include <hip/hip_runtime.h>
+
+#include "hexval_internal.hpp"
+#include "hexval_kernels.hpp"
+#include "hexval_math.hpp"
+
+namespace hexval {
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int lane_rank(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ unsigned long long wave_bcast(unsigned long long v, int src)
+{
+    return __shfl(v, src, 64);
+}
+
+// Reserves `count` consecutive slots of counter `c` for the lanes of `mask`;
+// returns this lane's slot (valid only for lanes in mask).
+__device__ __forceinline__ unsigned long long wave_reserve(unsigned long long* c, uint64_t mask)
+{
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(c, (unsigned long long)__popcll(mask));
+    base = wave_bcast(base, leader);
+    return base + (unsigned long long)lane_rank(mask);
+}
+
+__device__ __forceinline__ uint64_t load_acquire(const uint64_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_release(uint64_t* p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned long long load_relaxed(unsigned long long* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------- gather
+
+__device__ __forceinline__ void load_points(const MeshDev& m, int64_t e, V3 p[8], bool& bad_index)
+{
+    if (m.conn) {
+        const int4* cp = reinterpret_cast<const int4*>(m.conn + 8 * e);
+        const int4 q0 = cp[0], q1 = cp[1];
+        const int idx[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+        if (m.validate) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                bad_index |= (idx[k] < 0) || ((int64_t)idx[k] >= m.n_points);
+            if (bad_index) return;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double* v = m.points + 3 * (int64_t)idx[k];
+            p[k] = {v[0], v[1], v[2]};
+        }
+    } else {
+        const double* v = m.points + 24 * e;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) p[k] = {v[3 * k], v[3 * k + 1], v[3 * k + 2]};
+    }
+}
+
+// Writes a top-level node for a subdivided element.
+__device__ void write_root(Node* nd, const ElementValues& r, int64_t slot)
+{
+#pragma unroll
+    for (int a = 0; a < 27; ++a) nd->b[fig3_to_tensor(a)] = coefficient(r, a);
+    nd->scale = r.scale;
+    nd->slot = slot;
+    nd->level = 0;
+    nd->orient = 0;
+}
+
+// One element: decides, writes outputs, takes part in the wave's queue and
+// exact-list compaction (every lane of the wave must call this).
+__device__ void process_element(const MeshDev& m, int mesh_idx, int64_t e, bool active,
+                                const QueueDev& q, int max_depth)
+{
+    V3 p[8];
+    bool bad = false;
+    int st = -1;
+    ElementValues r;
+    Summary s;
+    if (active) {
+        load_points(m, e, p, bad);
+        if (!bad) {
+            element_values(p, r);
+            s = summarize(r);
+            st = top_state(r, s, max_depth);
+        }
+    }
+    const bool push = active && st == kTopSubdivide;
+    const bool exact = active && st == kTopExact;
+    uint8_t v = 0;
+    if (active) {
+        if (bad) v = 3;
+        else if (st <= kTopUndecided) v = (uint8_t)st;
+    }
+    const uint64_t pmask = ballot(push);
+    if (pmask) {
+        const unsigned long long slot = wave_reserve(&q.cnt->node_tail, pmask);
+        const unsigned long long sslot = wave_reserve(&q.cnt->n_sub, pmask);
+        const bool stored = push && slot < q.node_cap && sslot < q.node_cap;
+        const uint64_t smask = ballot(stored);
+        const int lane = threadIdx.x & 63;
+        if (smask && lane == __ffsll((unsigned long long)pmask) - 1)
+            atomicAdd(&q.cnt->outstanding, (unsigned long long)__popcll(smask));
+        if (stored) {
+            q.sub_elem[sslot] = e;
+            q.sub_mesh[sslot] = mesh_idx;
+            q.sub_flags[sslot] = 0u;
+            Node* nd = q.nodes + slot;
+            write_root(nd, r, (int64_t)sslot);
+            store_release(&nd->ready, q.epoch);
+            v = kPending;
+        } else if (push) {
+            if (sslot < q.node_cap) q.sub_elem[sslot] = -1;   // reserved but unused
+            v = kDeferred;
+            atomicAdd(&q.cnt->n_deferred, 1ull);
+        }
+    }
+    const uint64_t xmask = ballot(exact);
+    if (xmask) {
+        const unsigned long long slot = wave_reserve(&q.cnt->n_exact, xmask);
+        if (exact) {
+            if (slot < q.exact_cap) {
+                q.exact_elem[slot] = e;
+                q.exact_mesh[slot] = mesh_idx;
+                v = kExact;
+            } else {
+                v = kDeferred;
+                atomicAdd(&q.cnt->n_deferred, 1ull);
+            }
+        }
+    }
+    if (active) {
+        m.verdict[e] = v;
+        if (m.min_coeff) m.min_coeff[e] = bad ? __builtin_nan("") : s.min27;
+    }
+}
+
+// Tile order: with `xcds` chunks (8 on MI355X) the tiles are split into
+// contiguous chunks, chunk x processed by the blocks that the dispatcher
+// places on XCD x (block b runs on XCD b % 8), so neighbouring tiles, which
+// share vertices, meet in the same L2.
+struct TileIter {
+    int64_t t, end, step;
+    __device__ TileIter(int64_t n_tiles, int xcds)
+    {
+        const int64_t G = gridDim.x;
+        const int64_t x = blockIdx.x % xcds, local = blockIdx.x / xcds, per = G / xcds;
+        const int64_t cs = n_tiles * x / xcds, ce = n_tiles * (x + 1) / xcds;
+        t = cs + local;
+        end = ce;
+        step = per;
+    }
+};
+
+template <bool BATCHED>
+__global__ __launch_bounds__(256) void k_top_f64_range(TopArgs a)
+{
+    for (TileIter it(a.n_tiles, a.xcds); it.t < it.end; it.t += it.step) {
+        MeshDev m;
+        int mi;
+        int64_t e;
+        if (BATCHED) {
+            mi = a.tile_mesh[it.t];
+            m = a.meshes[mi];
+            e = (it.t - m.tile_begin) * (int64_t)blockDim.x + threadIdx.x;
+        } else {
+            mi = 0;
+            m = a.mesh;
+            e = it.t * (int64_t)blockDim.x + threadIdx.x;
+        }
+        process_element(m, mi, e, e < m.n, a.q, a.max_depth);
+    }
+}
+
+template <bool BATCHED>
+__global__ __launch_bounds__(256) void k_top_f64_list(TopArgs a)
+{
+    const unsigned long long cnt = *a.list_count;
+    const int64_t n = (int64_t)(cnt < a.q.list_cap ? cnt : a.q.list_cap);
+    const int64_t n_tiles = (n + blockDim.x - 1) / blockDim.x;
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const int64_t i = t * blockDim.x + threadIdx.x;
+        const bool active = i < n;
+        int mi = 0;
+        int64_t e = 0;
+        if (active) {
+            e = a.q.list_elem[i];
+            mi = a.q.list_mesh[i];
+        }
+        const MeshDev m = BATCHED && active ? a.meshes[mi] : a.mesh;
+        process_element(m, mi, e, active, a.q, a.max_depth);
+    }
+}
+
+// ------------------------------------------------------------ subdivision
+
+__device__ __forceinline__ int mirrored(int t, int pattern)
+{
+    const int i = t % 3, j = (t / 3) % 3, k = t / 9;
+    const int mi = (pattern & 1) ? 2 - i : i;
+    const int mj = (pattern & 2) ? 2 - j : j;
+    const int mk = (pattern & 4) ? 2 - k : k;
+    return mi + 3 * mj + 9 * mk;
+}
+
+__global__ __launch_bounds__(256) void k_drain(DrainArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 3;
+    const int child = lane & 7;
+    const QueueDev& q = a.q;
+    Counters* cnt = q.cnt;
+    const uint64_t cap = q.node_cap;
+    uint64_t idle_since = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+        unsigned long long h = 0;
+        if (lane == 0) h = atomicAdd(&cnt->node_head, 8ull);
+        h = wave_bcast(h, 0);
+        if (h >= cap) return;
+        const uint64_t slot = h + grp;
+        bool pending = slot < cap;
+        while (ballot(pending)) {
+            const bool ready = pending && load_acquire(&q.nodes[slot].ready) == q.epoch;
+            const uint64_t rmask = ballot(ready);
+            if (rmask) {
+                // ---- one child of a ready node per lane
+                bool push = false, invalid = false, undecided = false, inexact = false;
+                double t[27];
+                int level = 0;
+                int64_t sslot = 0;
+                double scale = 0.0;
+                if (ready) {
+                    const Node* nd = q.nodes + slot;
+                    const int pat = nd->orient ^ child;
+                    level = nd->level + 1;
+                    sslot = nd->slot;
+                    scale = nd->scale;
+#pragma unroll
+                    for (int k = 0; k < 27; ++k) t[k] = nd->b[mirrored(k, pat)];
+                    const bool dead =
+                        (__hip_atomic_load(q.sub_flags + sslot, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT) & kFlagInvalid) != 0u;
+                    if (!dead) {
+                        lower_octant(t);
+                        const double tau = level_threshold(scale, level);
+                        const double m8 = fmin(fmin(fmin(t[0], t[2]), fmin(t[6], t[8])),
+                                               fmin(fmin(t[18], t[20]), fmin(t[24], t[26])));
+                        double m19 = t[1];
+#pragma unroll
+                        for (int k = 3; k < 26; ++k)
+                            if (k != 6 && k != 8 && k != 18 && k != 20 && k != 24) m19 = fmin(m19, t[k]);
+                        if (m8 <= -tau) invalid = true;
+                        else if (!(m8 > tau)) inexact = true;
+                        else if (m19 > tau) { /* positive on this sub-box */ }
+                        else if (level < a.max_depth) push = true;
+                        else if (m19 <= -tau) undecided = true;
+                        else inexact = true;
+                    }
+                }
+                const uint32_t fl = (invalid ? kFlagInvalid : 0u) | (undecided ? kFlagUndecided : 0u) |
+                                    (inexact ? kFlagExact : 0u);
+                const uint64_t pmask = ballot(push);
+                if (pmask) {
+                    const unsigned long long ns = wave_reserve(&cnt->node_tail, pmask);
+                    const bool stored = push && ns < cap;
+                    const uint64_t smask = ballot(stored);
+                    if (smask && lane == __ffsll((unsigned long long)pmask) - 1)
+                        atomicAdd(&cnt->outstanding, (unsigned long long)__popcll(smask));
+                    if (stored) {
+                        Node* out = q.nodes + ns;
+#pragma unroll
+                        for (int k = 0; k < 27; ++k) out->b[k] = t[k];
+                        out->scale = scale;
+                        out->slot = sslot;
+                        out->level = level;
+                        out->orient = child;
+                        store_release(&out->ready, q.epoch);
+                    } else if (push) {
+                        atomicOr(q.sub_flags + sslot, kFlagOverflow);
+                    }
+                }
+                if (fl) atomicOr(q.sub_flags + sslot, fl);
+                if (lane == 0) {
+                    const unsigned int nproc = (unsigned int)(__popcll(rmask) / 8);
+                    atomicAdd(&cnt->n_nodes, (unsigned long long)__popcll(rmask));
+                    atomicSub(&cnt->outstanding, (unsigned long long)nproc);
+                }
+                if (ready) atomicMax(&cnt->max_level, (unsigned int)level);
+                pending = pending && !ready;
+                idle_since = __builtin_amdgcn_s_memrealtime();
+                continue;
+            }
+            unsigned long long out = 0;
+            if (lane == 0) out = load_relaxed(&cnt->outstanding);
+            out = wave_bcast(out, 0);
+            if (out == 0) return;
+            __builtin_amdgcn_s_sleep(2);
+            // 100 MHz real-time clock: give up after 4 s without progress.
+            if (__builtin_amdgcn_s_memrealtime() - idle_since > 400000000ull) {
+                if (lane == 0) atomicOr(&cnt->error, kErrSpinTimeout);
+                return;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fold(FoldArgs a)
+{
+    const QueueDev& q = a.q;
+    const unsigned long long ns = *(&q.cnt->n_sub);
+    const int64_t n = (int64_t)(ns < q.node_cap ? ns : q.node_cap);
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = q.sub_elem[s];
+        if (e < 0) continue;
+        const uint32_t f = q.sub_flags[s];
+        const int mi = q.sub_mesh[s];
+        const MeshDev m = a.meshes ? a.meshes[mi] : a.mesh;
+        uint8_t v;
+        if (f & kFlagInvalid) {
+            v = 0;
+        } else if (f & kFlagExact) {
+            const unsigned long long x = atomicAdd(&q.cnt->n_exact, 1ull);
+            if (x < q.exact_cap) {
+                q.exact_elem[x] = e;
+                q.exact_mesh[x] = mi;
+                v = kExact;
+            } else {
+                v = kDeferred;
+                atomicAdd(&q.cnt->n_deferred, 1ull);
+            }
+        } else if (f & kFlagOverflow) {
+            v = kDeferred;
+            atomicAdd(&q.cnt->n_deferred, 1ull);
+        } else if (f & kFlagUndecided) {
+            v = 2;
+        } else {
+            v = 1;
+        }
+        m.verdict[e] = v;
+    }
+}
+
+// ------------------------------------------------------------ small kernels
+
+__global__ void k_reset(Counters* c)
+{
+    unsigned long long* w = reinterpret_cast<unsigned long long*>(c);
+    const int nw = (int)(sizeof(Counters) / sizeof(unsigned long long));
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) w[i] = 0ull;
+}
+
+__global__ void k_tile_table(const MeshDev* meshes, int n_meshes, int tile, int32_t* tile_mesh)
+{
+    for (int mi = blockIdx.x; mi < n_meshes; mi += gridDim.x) {
+        const MeshDev m = meshes[mi];
+        const int64_t nt = (m.n + tile - 1) / tile;
+        for (int64_t t = threadIdx.x; t < nt; t += blockDim.x) tile_mesh[m.tile_begin + t] = mi;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_collect_deferred(CollectArgs a)
+{
+    for (int mi = 0; mi < a.n_meshes; ++mi) {
+        const MeshDev m = a.meshes ? a.meshes[mi] : a.mesh;
+        for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m.n;
+             e += (int64_t)gridDim.x * blockDim.x) {
+            const bool d = m.verdict[e] == kDeferred;
+            const uint64_t mask = ballot(d);
+            if (mask) {
+                const unsigned long long s = wave_reserve(&a.q.cnt->n_list, mask);
+                if (d && s < a.q.list_cap) {
+                    a.q.list_elem[s] = e;
+                    a.q.list_mesh[s] = mi;
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_gather_exact(GatherArgs a)
+{
+    const int64_t n = a.n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int mi = a.q.exact_mesh[i];
+        const MeshDev m = a.meshes ? a.meshes[mi] : a.mesh;
+        V3 p[8];
+        bool bad = false;
+        load_points(m, a.q.exact_elem[i], p, bad);
+        double* o = a.out + 24 * i;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            o[3 * k] = p[k].x;
+            o[3 * k + 1] = p[k].y;
+            o[3 * k + 2] = p[k].z;
+        }
+    }
+}
+
+__global__ void k_scatter_exact(ScatterArgs a)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < a.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int mi = a.q.exact_mesh[i];
+        const MeshDev m = a.meshes ? a.meshes[mi] : a.mesh;
+        const int64_t e = a.q.exact_elem[i];
+        const uint8_t v = a.verdicts[i];
+        m.verdict[e] = v;
+        if (v == 3 && m.min_coeff) m.min_coeff[e] = __builtin_nan("");
+    }
+}
+
+__global__ __launch_bounds__(256) void k_coefficients(MeshDev m, double* out)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m.n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        V3 p[8];
+        bool bad = false;
+        load_points(m, e, p, bad);
+        ElementValues r;
+        element_values(p, r);
+#pragma unroll
+        for (int a = 0; a < 27; ++a) out[27 * e + a] = coefficient(r, a);
+    }
+}
+
+// ------------------------------------------------------------ launchers
+
+#define HX_LAUNCH(kernel, grid, block, stream, ...) \
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, (hipStream_t)(stream), __VA_ARGS__)
+
+void launch_top_range(const TopArgs& a, bool batched, int grid, int block, hipStream_t s)
+{
+    if (batched) HX_LAUNCH(k_top_f64_range<true>, grid, block, s, a);
+    else HX_LAUNCH(k_top_f64_range<false>, grid, block, s, a);
+}
+
+void launch_top_list(const TopArgs& a, bool batched, int grid, int block, hipStream_t s)
+{
+    if (batched) HX_LAUNCH(k_top_f64_list<true>, grid, block, s, a);
+    else HX_LAUNCH(k_top_f64_list<false>, grid, block, s, a);
+}
+
+void launch_drain(const DrainArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_drain, grid, 256, s, a); }
+void launch_fold(const FoldArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_fold, grid, 256, s, a); }
+void launch_reset(Counters* c, hipStream_t s) { HX_LAUNCH(k_reset, 1, 64, s, c); }
+void launch_tile_table(const MeshDev* meshes, int n_meshes, int tile, int32_t* tile_mesh, hipStream_t s)
+{
+    HX_LAUNCH(k_tile_table, n_meshes < 4096 ? n_meshes : 4096, 256, s, meshes, n_meshes, tile, tile_mesh);
+}
+void launch_collect_deferred(const CollectArgs& a, int grid, hipStream_t s)
+{
+    HX_LAUNCH(k_collect_deferred, grid, 256, s, a);
+}
+void launch_gather_exact(const GatherArgs& a, hipStream_t s)
+{
+    const int64_t g = (a.n + 255) / 256;
+    HX_LAUNCH(k_gather_exact, g < 1024 ? g : 1024, 256, s, a);
+}
+void launch_scatter_exact(const ScatterArgs& a, hipStream_t s)
+{
+    const int64_t g = (a.n + 255) / 256;
+    HX_LAUNCH(k_scatter_exact, g < 1024 ? g : 1024, 256, s, a);
+}
+void launch_coefficients(const MeshDev& m, double* out, hipStream_t s)
+{
+    const int64_t g = (m.n + 255) / 256;
+    HX_LAUNCH(k_coefficients, g < 65536 ? g : 65536, 256, s, m, out);
+}
+
+}  // namespace hexval

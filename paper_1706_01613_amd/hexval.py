@@ -1,0 +1,241 @@
+"""Thin Python binding of libhexval (ctypes; argument marshalling only).
+
+Every function of ``include/hexval.h`` is exposed under the same name.  Array
+arguments may be ROCm torch tensors (their ``data_ptr()`` is passed) or raw
+integer device addresses; every step of the check runs in the HIP library.
+The library is loaded on first use; if it has not been built this raises
+``HexvalError`` (there is no fallback).
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhexval.so")
+
+INVALID, VALID, UNDECIDED, BAD_INPUT = 0, 1, 2, 3
+OK, E_ARG, E_HIP, E_NOMEM, E_QUEUE, E_BUSY = 0, 1, 2, 3, 4, 5
+FP64, FP32_FILTER = 0, 1
+STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_HIP", 3: "E_NOMEM", 4: "E_QUEUE", 5: "E_BUSY"}
+
+
+class HexvalError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"hexval {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class hexval_mesh_t(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("n_points", ctypes.c_int64),
+                ("connectivity", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
+class hexval_stats_t(ctypes.Structure):
+    _fields_ = [("n_elements", ctypes.c_int64), ("n_subdivided", ctypes.c_int64),
+                ("n_nodes", ctypes.c_int64), ("n_exact", ctypes.c_int64),
+                ("n_recheck", ctypes.c_int64), ("n_rounds", ctypes.c_int64),
+                ("max_level", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("ms_first_pass", ctypes.c_float), ("ms_recheck", ctypes.c_float),
+                ("ms_subdivision", ctypes.c_float), ("ms_total", ctypes.c_float)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class hexval_opts_t(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("max_depth", ctypes.c_int32),
+                ("validate_indices", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("queue_capacity", ctypes.c_int64), ("grid_blocks", ctypes.c_int64),
+                ("stream", ctypes.c_void_p), ("stats", ctypes.POINTER(hexval_stats_t))]
+
+
+class hexval_request_t(ctypes.Structure):
+    _fields_ = [("mesh", hexval_mesh_t), ("host_points", ctypes.c_void_p),
+                ("host_conn", ctypes.c_void_p), ("verdicts", ctypes.c_void_p),
+                ("min_coeffs", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libhexval (raises HexvalError when it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HexvalError(E_HIP, f"{LIB_PATH} is not built; run "
+                                     "python -m paper_1706_01613_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        sig = {
+            "hexval_opts_default": (None, [ctypes.POINTER(hexval_opts_t)]),
+            "hexval_check": (ctypes.c_int, [P, P, I64, P, P]),
+            "hexval_check_ex": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t),
+                                               ctypes.POINTER(hexval_opts_t), P, P]),
+            "hexval_check_batched": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t), I32,
+                                                    ctypes.POINTER(hexval_opts_t), P, P]),
+            "hexval_coefficients": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t), P, P]),
+            "hexval_server_create": (ctypes.c_int, [ctypes.POINTER(hexval_opts_t), I64, I32,
+                                                    ctypes.POINTER(P)]),
+            "hexval_server_submit": (ctypes.c_int, [P, ctypes.POINTER(hexval_request_t),
+                                                    ctypes.POINTER(ctypes.c_uint64)]),
+            "hexval_server_poll": (ctypes.c_int, [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                                                  ctypes.POINTER(ctypes.c_double)]),
+            "hexval_server_wait": (ctypes.c_int, [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]),
+            "hexval_server_destroy": (ctypes.c_int, [P]),
+            "hexval_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _addr(x):
+    """Device address of a torch tensor, an int, or None (NULL)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _check(status):
+    if status != OK:
+        raise HexvalError(status, lib().hexval_last_error().decode(errors="replace"))
+    return status
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def hexval_opts_default():
+    o = hexval_opts_t()
+    lib().hexval_opts_default(ctypes.byref(o))
+    return o
+
+
+def make_opts(precision=FP64, max_depth=6, validate_indices=False, block_threads=0,
+              queue_capacity=0, grid_blocks=0, stream=None, stats=None):
+    o = hexval_opts_default()
+    o.precision = precision
+    o.max_depth = max_depth
+    o.validate_indices = int(bool(validate_indices))
+    o.block_threads = block_threads
+    o.queue_capacity = queue_capacity
+    o.grid_blocks = grid_blocks
+    o.stream = _stream_handle(stream)
+    if stats is not None:
+        o.stats = ctypes.pointer(stats)
+    return o
+
+
+def make_mesh(points, connectivity=None, n=None, n_points=None):
+    if n is None:
+        n = connectivity.shape[0] if connectivity is not None else points.shape[0]
+    if n_points is None:
+        n_points = points.shape[0] if connectivity is not None and hasattr(points, "shape") else 0
+    return hexval_mesh_t(_addr(points), int(n_points), _addr(connectivity), int(n))
+
+
+def hexval_check(points, connectivity, n, verdicts, min_coeffs=None):
+    """C: hexval_check.  Raises HexvalError on a non-OK status."""
+    return _check(lib().hexval_check(_addr(points), _addr(connectivity), int(n),
+                                     _addr(verdicts), _addr(min_coeffs)))
+
+
+def hexval_check_ex(mesh, opts, verdicts, min_coeffs=None):
+    """C: hexval_check_ex (mesh: hexval_mesh_t, opts: hexval_opts_t or None)."""
+    return _check(lib().hexval_check_ex(ctypes.byref(mesh), ctypes.byref(opts) if opts else None,
+                                        _addr(verdicts), _addr(min_coeffs)))
+
+
+def hexval_check_batched(meshes, opts, verdicts, min_coeffs=None):
+    """C: hexval_check_batched (meshes: list of hexval_mesh_t; verdicts and
+    min_coeffs: lists of tensors/addresses, min_coeffs entries may be None)."""
+    n = len(meshes)
+    arr = (hexval_mesh_t * n)(*meshes)
+    v = (ctypes.c_void_p * n)(*[_addr(x) for x in verdicts])
+    m = (ctypes.c_void_p * n)(*[_addr(x) for x in min_coeffs]) if min_coeffs is not None else None
+    return _check(lib().hexval_check_batched(arr, n, ctypes.byref(opts) if opts else None,
+                                             ctypes.cast(v, ctypes.c_void_p),
+                                             ctypes.cast(m, ctypes.c_void_p) if m is not None else None))
+
+
+def hexval_coefficients(mesh, stream, coeffs):
+    """C: hexval_coefficients."""
+    return _check(lib().hexval_coefficients(ctypes.byref(mesh), _stream_handle(stream), _addr(coeffs)))
+
+
+def hexval_server_create(opts, hbm_budget_bytes, max_slots):
+    h = ctypes.c_void_p()
+    _check(lib().hexval_server_create(ctypes.byref(opts) if opts else None, int(hbm_budget_bytes),
+                                      int(max_slots), ctypes.byref(h)))
+    return h
+
+
+def hexval_server_submit(server, request):
+    t = ctypes.c_uint64()
+    _check(lib().hexval_server_submit(server, ctypes.byref(request), ctypes.byref(t)))
+    return t.value
+
+
+def hexval_server_poll(server, ticket):
+    done = ctypes.c_int()
+    lat = ctypes.c_double()
+    _check(lib().hexval_server_poll(server, ticket, ctypes.byref(done), ctypes.byref(lat)))
+    return bool(done.value), (lat.value if done.value else None)
+
+
+def hexval_server_wait(server, ticket):
+    lat = ctypes.c_double()
+    _check(lib().hexval_server_wait(server, ticket, ctypes.byref(lat)))
+    return lat.value
+
+
+def hexval_server_destroy(server):
+    return _check(lib().hexval_server_destroy(server))
+
+
+def hexval_last_error():
+    return lib().hexval_last_error().decode(errors="replace")
+
+
+# ---------------------------------------------------------------- conveniences
+
+def check(points, connectivity=None, precision=FP64, max_depth=6, validate_indices=False,
+          stream=None, stats=False, block_threads=0, grid_blocks=0, queue_capacity=0,
+          want_min=True):
+    """Allocate outputs (torch, on points' device) and run hexval_check_ex.
+
+    points: [n,8,3] float64 (connectivity None) or [m,3] float64 with
+    connectivity [n,8] int32.  Returns (verdicts uint8 [n], min_coeffs float64
+    [n] or None, stats dict or None)."""
+    import torch
+    n = connectivity.shape[0] if connectivity is not None else points.shape[0]
+    verdicts = torch.empty(n, dtype=torch.uint8, device=points.device)
+    mins = torch.empty(n, dtype=torch.float64, device=points.device) if want_min else None
+    st = hexval_stats_t()
+    st.timing = 1 if stats else 0
+    if stream is None:
+        stream = torch.cuda.current_stream(points.device)
+    opts = make_opts(precision, max_depth, validate_indices, block_threads, queue_capacity,
+                     grid_blocks, stream, st)
+    hexval_check_ex(make_mesh(points, connectivity, n), opts, verdicts, mins)
+    return verdicts, mins, (st.as_dict() if stats else None)
+
+
+def coefficients(points, connectivity=None, stream=None):
+    import torch
+    n = connectivity.shape[0] if connectivity is not None else points.shape[0]
+    out = torch.empty((n, 27), dtype=torch.float64, device=points.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(points.device)
+    hexval_coefficients(make_mesh(points, connectivity, n), stream, out)
+    return out

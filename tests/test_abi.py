@@ -1,0 +1,91 @@
+"""The C ABI library loads, exports every declared symbol and rejects bad
+arguments without touching a GPU (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1706_01613_amd import hexval as hx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hexval.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hexval_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert "hexval_check" in names and "hexval_server_submit" in names
+    L = hx.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_struct_layouts_match_header_sizes():
+    # int64 alignment: mesh 32 B, opts 48 B, stats 72 B, request 64 B
+    assert ctypes.sizeof(hx.hexval_mesh_t) == 32
+    assert ctypes.sizeof(hx.hexval_opts_t) == 48
+    assert ctypes.sizeof(hx.hexval_stats_t) == 72
+    assert ctypes.sizeof(hx.hexval_request_t) == 64
+
+
+def test_defaults():
+    o = hx.hexval_opts_default()
+    assert (o.precision, o.max_depth, o.validate_indices, o.queue_capacity) == (hx.FP64, 6, 0, 0)
+
+
+def _status(f, *args):
+    try:
+        return f(*args)
+    except hx.HexvalError as e:
+        return e.status
+
+
+def test_argument_errors_without_gpu():
+    L = hx.lib()
+    assert L.hexval_check(None, None, 0, None, None) == hx.OK          # n == 0: no-op
+    assert L.hexval_check(None, None, -1, None, None) == hx.E_ARG
+    assert L.hexval_check(None, None, 5, 1, None) == hx.E_ARG          # NULL points
+    assert "points" in hx.hexval_last_error()
+    assert L.hexval_check(16, None, 5, None, None) == hx.E_ARG         # NULL verdicts
+    assert L.hexval_check_ex(None, None, None, None) == hx.E_ARG
+    mesh = hx.hexval_mesh_t(16, 0, None, 4)
+    for field, value in [("max_depth", 21), ("max_depth", -1), ("precision", 7),
+                         ("block_threads", 100), ("block_threads", 512), ("queue_capacity", -5)]:
+        o = hx.hexval_opts_default()
+        setattr(o, field, value)
+        assert L.hexval_check_ex(ctypes.byref(mesh), ctypes.byref(o), 32, None) == hx.E_ARG, field
+    o = hx.hexval_opts_default()
+    o.validate_indices = 1
+    mesh = hx.hexval_mesh_t(16, 0, 32, 4)                               # n_points missing
+    assert L.hexval_check_ex(ctypes.byref(mesh), ctypes.byref(o), 32, None) == hx.E_ARG
+    assert L.hexval_check_batched(None, -1, None, None, None) == hx.E_ARG
+    assert L.hexval_coefficients(None, None, None) == hx.E_ARG
+    h = ctypes.c_void_p()
+    assert L.hexval_server_create(None, 0, 1, ctypes.byref(h)) == hx.E_ARG
+    assert L.hexval_server_create(None, 1 << 30, 0, ctypes.byref(h)) == hx.E_ARG
+    assert L.hexval_server_destroy(None) == hx.E_ARG
+
+
+def test_no_device_reports_hip_error():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present; this case covers hosts without one")
+    L = hx.lib()
+    # valid-looking arguments: the library must stop at the device check
+    assert L.hexval_check(16, None, 4, 32, None) == hx.E_HIP
+    assert "device" in hx.hexval_last_error()
+    h = ctypes.c_void_p()
+    assert L.hexval_server_create(None, 1 << 34, 2, ctypes.byref(h)) == hx.E_HIP
+
+
+def test_binding_names_match_the_abi():
+    for name in declared_functions():
+        if name == "hexval_opts_default":
+            continue
+        assert hasattr(hx, name), name

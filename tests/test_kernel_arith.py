@@ -1,0 +1,126 @@
+"""CPU replay of the kernels' arithmetic (libhexval_emul.so) against the
+oracle: the error bounds the kernels certify with, their decision logic and
+the library's exact tier (CPU only; the GPU parity tests run the kernels)."""
+import ctypes
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact
+from paper_1706_01613_amd import synth
+from paper_1706_01613_amd.build import EMUL
+
+CUBE = synth.CUBE
+
+
+@pytest.fixture(scope="module")
+def emul():
+    E = ctypes.CDLL(EMUL)
+    P = ctypes.c_void_p
+    E.hexval_emul_check.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, P, P, P]
+    E.hexval_emul_values.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, P, P, P, P]
+    E.hexval_emul_exact.argtypes = [P, ctypes.c_int64, ctypes.c_int, P]
+    E.hexval_emul_constants.argtypes = [P]
+    return E
+
+
+def run_check(E, pts, conn=None, max_depth=6):
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    n = conn.shape[0] if conn is not None else pts.shape[0]
+    v = np.empty(n, np.uint8)
+    m = np.empty(n)
+    st = np.zeros(4, np.int64)
+    E.hexval_emul_check(pts.ctypes.data, None if conn is None else conn.ctypes.data, n,
+                        max_depth, v.ctypes.data, m.ctypes.data, st.ctypes.data)
+    return v, m, st
+
+
+def values(E, pts):
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 8, 3)
+    n = pts.shape[0]
+    c = np.empty((n, 27))
+    s = np.empty(n)
+    E.hexval_emul_values(pts.ctypes.data, None, n, 6, c.ctypes.data, s.ctypes.data, None, None)
+    return c, s
+
+
+def test_config1_subset_matches_oracle(emul):
+    X = synth.independent_hexes(200000, seed=0)
+    v, m, st = run_check(emul, X)
+    r = oracle.check(X)
+    assert (v == r["verdict"]).all()
+    b = oracle.coefficients(X)
+    assert (np.abs(m - r["min_coeff"]) / np.abs(b).max(1)).max() < 1e-12
+    assert st[0] > 0
+
+
+@pytest.mark.parametrize("max_depth", [0, 1, 2, 6, 9])
+def test_tangled_and_lattice_match_oracle(emul, max_depth):
+    X = synth.independent_hexes(30000, noise=0.5, seed=max_depth)
+    v, _, _ = run_check(emul, X, max_depth=max_depth)
+    assert (v == oracle.check(X, max_depth=max_depth)["verdict"]).all()
+    V, C = synth.warped_lattice(24, 20, 16, jitter_fraction=0.1, seed=max_depth)
+    v, _, _ = run_check(emul, V, C, max_depth=max_depth)
+    assert (v == oracle.check(V, C, max_depth=max_depth)["verdict"]).all()
+
+
+def test_precision_stress_hexes_match_oracle(emul):
+    P = synth.near_degenerate_hexes(20000, seed=1)
+    v, _, _ = run_check(emul, P)
+    r = oracle.check(P)
+    assert (v == r["verdict"]).all()
+    assert 0.3 < (r["verdict"] == 0).mean() < 0.7
+
+
+def test_integer_lattice_and_exact_tier(emul):
+    rng = np.random.default_rng(4)
+    P = (CUBE[None] * 2 + rng.integers(-1, 2, size=(3000, 8, 3))).astype(np.float64)
+    v, _, st = run_check(emul, P)
+    assert st[2] > 0                       # exact tier used
+    assert (v == oracle.check(P)["verdict"]).all()
+    # the library's exact tier alone against the oracle's rational tier
+    out = np.empty(300, np.uint8)
+    emul.hexval_emul_exact(np.ascontiguousarray(P[:300]).ctypes.data, 300, 6, out.ctypes.data)
+    assert list(out) == [exact.validity(p)["verdict"] for p in P[:300]]
+
+
+def test_exact_tier_on_random_and_degenerate(emul):
+    X = synth.independent_hexes(200, noise=0.5, seed=3)
+    X[:5] = 0.0
+    X[5, 2, 1] = np.nan
+    out = np.empty(len(X), np.uint8)
+    emul.hexval_emul_exact(np.ascontiguousarray(X).ctypes.data, len(X), 4, out.ctypes.data)
+    want = [exact.validity(p, max_depth=4)["verdict"] for p in X]
+    assert list(out) == want
+    assert want[5] == exact.BAD_INPUT and want[0] == exact.INVALID
+
+
+@pytest.mark.parametrize("kind", ["random", "offset", "flat", "scaled", "stress"])
+def test_kernel_error_bounds_hold(emul, kind):
+    """|b^ - b| < tau_coeff u M^ for b_9..b_27 and |c^ - c| < tau_value u M^ for
+    corner values, with exact ground truth."""
+    rng = np.random.default_rng(20 + len(kind))
+    n = 50
+    X = CUBE[None] + rng.uniform(-0.4, 0.4, size=(n, 8, 3))
+    if kind == "offset":
+        X = X + rng.uniform(100, 1000, size=(n, 1, 3))
+    if kind == "flat":
+        X[:, :, 2] *= 1e-9
+    if kind == "scaled":
+        X = X * 10.0 ** rng.uniform(-3, 3, size=(n, 1, 1))
+    if kind == "stress":
+        X = synth.near_degenerate_hexes(n, seed=5)
+    k = np.empty(4)
+    emul.hexval_emul_constants(k.ctypes.data)
+    tau_v, tau_b, _, u = k
+    c, s = values(emul, X)
+    worst = 0.0
+    for P, cc, m in zip(X, c, s):
+        be, _ = exact.coefficients(P)
+        for a in range(27):
+            e = abs(Fraction(float(cc[a])) - be[a])
+            t = (tau_v if a < 8 else tau_b) * u * m
+            worst = max(worst, float(e) / t)
+    assert worst < 1.0
