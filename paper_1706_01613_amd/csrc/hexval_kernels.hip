@@ -55,6 +55,11 @@ __device__ __forceinline__ void store_release(uint64_t* p, uint64_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ uint64_t load_relaxed64(const uint64_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ unsigned long long load_relaxed(unsigned long long* p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -62,13 +67,24 @@ __device__ __forceinline__ unsigned long long load_relaxed(unsigned long long* p
 
 // ---------------------------------------------------------------- gather
 
-__device__ __forceinline__ void load_points(const MeshDev& m, int64_t e, V3 p[8], bool& bad_index)
+// Gather modes: which layouts a kernel instantiation handles.
+enum Gather : int {
+    kGatherAny = 0,       // decided per mesh at run time
+    kGatherPoints = 1,    // [n,8,3] points
+    kGatherConn = 2,      // connectivity, trusted indices
+    kGatherChecked = 3    // connectivity, indices validated
+};
+
+template <int G>
+__device__ __forceinline__ void load_points_t(const MeshDev& m, int64_t e, V3 p[8], bool& bad_index)
 {
-    if (m.conn) {
+    const bool conn = G == kGatherAny ? m.conn != nullptr : G != kGatherPoints;
+    const bool validate = G == kGatherAny ? m.validate != 0 : G == kGatherChecked;
+    if (conn) {
         const int4* cp = reinterpret_cast<const int4*>(m.conn + 8 * e);
         const int4 q0 = cp[0], q1 = cp[1];
         const int idx[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
-        if (m.validate) {
+        if (validate) {
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 bad_index |= (idx[k] < 0) || ((int64_t)idx[k] >= m.n_points);
@@ -86,6 +102,11 @@ __device__ __forceinline__ void load_points(const MeshDev& m, int64_t e, V3 p[8]
     }
 }
 
+__device__ __forceinline__ void load_points(const MeshDev& m, int64_t e, V3 p[8], bool& bad_index)
+{
+    load_points_t<kGatherAny>(m, e, p, bad_index);
+}
+
 // Writes a top-level node for a subdivided element.
 __device__ void write_root(Node* nd, const ElementValues& r, int64_t slot)
 {
@@ -97,54 +118,48 @@ __device__ void write_root(Node* nd, const ElementValues& r, int64_t slot)
     nd->orient = 0;
 }
 
-// One element: decides, writes outputs, takes part in the wave's queue and
-// exact-list compaction (every lane of the wave must call this).
+// One element: decides, writes outputs, takes part in the wave's compaction
+// of subdivided and exact-tier elements into their lists (every lane of the
+// wave must call this).  Subdivided elements only get their id listed here;
+// k_roots recomputes their 27 coefficients, which keeps this kernel's
+// register footprint small.
+template <bool EDGES, int G>
 __device__ void process_element(const MeshDev& m, int mesh_idx, int64_t e, bool active,
                                 const QueueDev& q, int max_depth)
 {
     V3 p[8];
     bool bad = false;
     int st = -1;
-    ElementValues r;
-    Summary s;
+    double mn = 0.0;
     if (active) {
-        load_points(m, e, p, bad);
+        load_points_t<G>(m, e, p, bad);
         if (!bad) {
-            element_values(p, r);
-            s = summarize(r);
-            st = top_state(r, s, max_depth);
+            const LeanResult r = element_lean(p, EDGES);
+            st = lean_state(r, max_depth);
+            mn = r.min27;
         }
     }
-    const bool push = active && st == kTopSubdivide;
-    const bool exact = active && st == kTopExact;
     uint8_t v = 0;
     if (active) {
         if (bad) v = 3;
         else if (st <= kTopUndecided) v = (uint8_t)st;
     }
+    const bool push = active && st == kTopSubdivide;
     const uint64_t pmask = ballot(push);
     if (pmask) {
-        const unsigned long long slot = wave_reserve(&q.cnt->node_tail, pmask);
-        const unsigned long long sslot = wave_reserve(&q.cnt->n_sub, pmask);
-        const bool stored = push && slot < q.node_cap && sslot < q.node_cap;
-        const uint64_t smask = ballot(stored);
-        const int lane = threadIdx.x & 63;
-        if (smask && lane == __ffsll((unsigned long long)pmask) - 1)
-            atomicAdd(&q.cnt->outstanding, (unsigned long long)__popcll(smask));
-        if (stored) {
-            q.sub_elem[sslot] = e;
-            q.sub_mesh[sslot] = mesh_idx;
-            q.sub_flags[sslot] = 0u;
-            Node* nd = q.nodes + slot;
-            write_root(nd, r, (int64_t)sslot);
-            store_release(&nd->ready, q.epoch);
-            v = kPending;
-        } else if (push) {
-            if (sslot < q.node_cap) q.sub_elem[sslot] = -1;   // reserved but unused
-            v = kDeferred;
-            atomicAdd(&q.cnt->n_deferred, 1ull);
+        const unsigned long long slot = wave_reserve(&q.cnt->n_sub, pmask);
+        if (push) {
+            if (slot < q.node_cap) {
+                q.sub_elem[slot] = e;
+                q.sub_mesh[slot] = mesh_idx;
+                v = kPending;
+            } else {
+                v = kDeferred;
+                atomicAdd(&q.cnt->n_deferred, 1ull);
+            }
         }
     }
+    const bool exact = active && st == kTopExact;
     const uint64_t xmask = ballot(exact);
     if (xmask) {
         const unsigned long long slot = wave_reserve(&q.cnt->n_exact, xmask);
@@ -161,7 +176,35 @@ __device__ void process_element(const MeshDev& m, int mesh_idx, int64_t e, bool 
     }
     if (active) {
         m.verdict[e] = v;
-        if (m.min_coeff) m.min_coeff[e] = bad ? __builtin_nan("") : s.min27;
+        if (m.min_coeff) m.min_coeff[e] = bad ? __builtin_nan("") : mn;
+    }
+}
+
+// Root nodes of the subdivided elements listed by the first pass: the full
+// set of 27 coefficients is recomputed (same arithmetic as the first pass)
+// and written to queue slot s = list index.
+__global__ __launch_bounds__(256) void k_roots(RootArgs a)
+{
+    const QueueDev& q = a.q;
+    const unsigned long long ns = q.cnt->n_sub;
+    const int64_t n = (int64_t)(ns < q.node_cap ? ns : q.node_cap);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        q.cnt->node_tail = (unsigned long long)n;
+        q.cnt->outstanding = (unsigned long long)n;
+    }
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int mi = q.sub_mesh[s];
+        const MeshDev m = a.meshes ? a.meshes[mi] : a.mesh;
+        V3 p[8];
+        bool bad = false;
+        load_points(m, q.sub_elem[s], p, bad);
+        ElementValues r;
+        element_values(p, r);
+        Node* nd = q.nodes + s;
+        write_root(nd, r, s);
+        q.sub_flags[s] = 0u;
+        store_release(&nd->ready, q.epoch);
     }
 }
 
@@ -182,7 +225,9 @@ struct TileIter {
     }
 };
 
-template <bool BATCHED>
+// EDGES: include the edge-midpoint values in the step-2 test (needed only
+// when the depth cap is 0, see element_lean).
+template <bool BATCHED, bool EDGES, int G>
 __global__ __launch_bounds__(256) void k_top_f64_range(TopArgs a)
 {
     for (TileIter it(a.n_tiles, a.xcds); it.t < it.end; it.t += it.step) {
@@ -198,11 +243,11 @@ __global__ __launch_bounds__(256) void k_top_f64_range(TopArgs a)
             m = a.mesh;
             e = it.t * (int64_t)blockDim.x + threadIdx.x;
         }
-        process_element(m, mi, e, e < m.n, a.q, a.max_depth);
+        process_element<EDGES, G>(m, mi, e, e < m.n, a.q, a.max_depth);
     }
 }
 
-template <bool BATCHED>
+template <bool BATCHED, bool EDGES>
 __global__ __launch_bounds__(256) void k_top_f64_list(TopArgs a)
 {
     const unsigned long long cnt = *a.list_count;
@@ -218,7 +263,7 @@ __global__ __launch_bounds__(256) void k_top_f64_list(TopArgs a)
             mi = a.q.list_mesh[i];
         }
         const MeshDev m = BATCHED && active ? a.meshes[mi] : a.mesh;
-        process_element(m, mi, e, active, a.q, a.max_depth);
+        process_element<EDGES, kGatherAny>(m, mi, e, active, a.q, a.max_depth);
     }
 }
 
@@ -250,9 +295,12 @@ __global__ __launch_bounds__(256) void k_drain(DrainArgs a)
         const uint64_t slot = h + grp;
         bool pending = slot < cap;
         while (ballot(pending)) {
-            const bool ready = pending && load_acquire(&q.nodes[slot].ready) == q.epoch;
+            // Poll with relaxed loads (no cache maintenance per poll); one
+            // acquire fence once a node is seen complete.
+            const bool ready = pending && load_relaxed64(&q.nodes[slot].ready) == q.epoch;
             const uint64_t rmask = ballot(ready);
             if (rmask) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 // ---- one child of a ready node per lane
                 bool push = false, invalid = false, undecided = false, inexact = false;
                 double t[27];
@@ -462,17 +510,37 @@ __global__ __launch_bounds__(256) void k_coefficients(MeshDev m, double* out)
 
 void launch_top_range(const TopArgs& a, bool batched, int grid, int block, hipStream_t s)
 {
-    if (batched) HX_LAUNCH(k_top_f64_range<true>, grid, block, s, a);
-    else HX_LAUNCH(k_top_f64_range<false>, grid, block, s, a);
+    const bool edges = a.max_depth == 0;
+    if (batched) {
+        if (edges) HX_LAUNCH((k_top_f64_range<true, true, kGatherAny>), grid, block, s, a);
+        else HX_LAUNCH((k_top_f64_range<true, false, kGatherAny>), grid, block, s, a);
+        return;
+    }
+    const int g = !a.mesh.conn ? kGatherPoints : a.mesh.validate ? kGatherChecked : kGatherConn;
+#define HX_TOP(E, G) HX_LAUNCH((k_top_f64_range<false, E, G>), grid, block, s, a)
+    if (edges) {
+        if (g == kGatherPoints) HX_TOP(true, kGatherPoints);
+        else if (g == kGatherConn) HX_TOP(true, kGatherConn);
+        else HX_TOP(true, kGatherChecked);
+    } else {
+        if (g == kGatherPoints) HX_TOP(false, kGatherPoints);
+        else if (g == kGatherConn) HX_TOP(false, kGatherConn);
+        else HX_TOP(false, kGatherChecked);
+    }
+#undef HX_TOP
 }
 
 void launch_top_list(const TopArgs& a, bool batched, int grid, int block, hipStream_t s)
 {
-    if (batched) HX_LAUNCH(k_top_f64_list<true>, grid, block, s, a);
-    else HX_LAUNCH(k_top_f64_list<false>, grid, block, s, a);
+    const bool edges = a.max_depth == 0;
+    if (batched && edges) HX_LAUNCH((k_top_f64_list<true, true>), grid, block, s, a);
+    else if (batched) HX_LAUNCH((k_top_f64_list<true, false>), grid, block, s, a);
+    else if (edges) HX_LAUNCH((k_top_f64_list<false, true>), grid, block, s, a);
+    else HX_LAUNCH((k_top_f64_list<false, false>), grid, block, s, a);
 }
 
 void launch_drain(const DrainArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_drain, grid, 256, s, a); }
+void launch_roots(const RootArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_roots, grid, 256, s, a); }
 void launch_fold(const FoldArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_fold, grid, 256, s, a); }
 void launch_reset(Counters* c, hipStream_t s) { HX_LAUNCH(k_reset, 1, 64, s, c); }
 void launch_tile_table(const MeshDev* meshes, int n_meshes, int tile, int32_t* tile_mesh, hipStream_t s)

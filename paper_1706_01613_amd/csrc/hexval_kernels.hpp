@@ -23,6 +23,12 @@ struct DrainArgs {
     int32_t max_depth;
 };
 
+struct RootArgs {
+    QueueDev q;
+    MeshDev mesh;
+    const MeshDev* meshes;
+};
+
 struct FoldArgs {
     QueueDev q;
     MeshDev mesh;
@@ -55,6 +61,7 @@ struct ScatterArgs {
 void launch_top_range(const TopArgs& a, bool batched, int grid, int block, hipStream_t s);
 void launch_top_list(const TopArgs& a, bool batched, int grid, int block, hipStream_t s);
 void launch_drain(const DrainArgs& a, int grid, hipStream_t s);
+void launch_roots(const RootArgs& a, int grid, hipStream_t s);
 void launch_fold(const FoldArgs& a, int grid, hipStream_t s);
 void launch_reset(Counters* c, hipStream_t s);
 void launch_tile_table(const MeshDev* meshes, int n_meshes, int tile, int32_t* tile_mesh, hipStream_t s);

@@ -152,8 +152,8 @@ HEXVAL_HD void element_values(const V3 p[8], ElementValues& r)
     // Faces 21..26 = zeta=0, eta=0, xi=1, eta=1, xi=0, zeta=1: their corners
     // and edges (Fig. 3 numbering).
     const double cz0 = s01 + s23, cz1 = s45 + s67;
-    const double dz0 = (d[0] + d[1]) + (d[2] + d[3]);
-    const double dz1 = (d[8] + d[9]) + (d[10] + d[11]);
+    const double dz0 = (d[0] + d[2]) + (d[1] + d[3]);
+    const double dz1 = (d[8] + d[10]) + (d[9] + d[11]);
     const double dvert = (d[4] + d[5]) + (d[6] + d[7]);
     r.f[0] = fma(-3.0, cz0, dz0);                                   // 21: 1234 | 9 10 11 12
     r.f[1] = fma(-3.0, s01 + s45, (d[0] + d[8]) + (d[4] + d[5]));   // 22: 1256 | 9 13 14 17
@@ -265,6 +265,97 @@ HEXVAL_HD void lower_octant(double t[27])
         for (int i = 0; i < 3; ++i) left_half(t[i + 9 * k], t[i + 3 + 9 * k], t[i + 6 + 9 * k]);
 #pragma unroll
     for (int ij = 0; ij < 9; ++ij) left_half(t[ij], t[ij + 9], t[ij + 18]);
+}
+
+}  // namespace hexval
+
+namespace hexval {
+
+// The first-pass quantities only (no coefficient array): the same operations
+// and roundings as element_values + summarize, ordered so that the edge
+// values are consumed as soon as they are formed (fewer live registers).
+struct LeanResult {
+    double m20, mb, min27, scale;
+    bool certified_range;
+};
+
+// check_edges: also test the 12 edge-midpoint values in the step-2 minimum.
+// Without it an element whose only non-positive value sits at an edge
+// midpoint is sent to subdivision, where that midpoint is a corner of a
+// level-1 sub-box, so the verdict is the same whenever the depth cap is >= 1.
+HEXVAL_HD LeanResult element_lean(const V3 p[8], bool check_edges)
+{
+    const V3 a00 = sub3(p[1], p[0]), a10 = sub3(p[2], p[3]);
+    const V3 a01 = sub3(p[5], p[4]), a11 = sub3(p[6], p[7]);
+    const V3 b00 = sub3(p[3], p[0]), b10 = sub3(p[2], p[1]);
+    const V3 b01 = sub3(p[7], p[4]), b11 = sub3(p[6], p[5]);
+    const V3 c00 = sub3(p[4], p[0]), c10 = sub3(p[5], p[1]);
+    const V3 c01 = sub3(p[7], p[3]), c11 = sub3(p[6], p[2]);
+    const double sx = fmax(fmax(amax(fabs(a00.x), a10), amax(fabs(a00.y), a01)), amax(fabs(a00.z), a11));
+    const double sy = fmax(fmax(amax(fabs(b00.x), b10), amax(fabs(b00.y), b01)), amax(fabs(b00.z), b11));
+    const double sz = fmax(fmax(amax(fabs(c00.x), c10), amax(fabs(c00.y), c01)), amax(fabs(c00.z), c11));
+
+    const double c0 = triple(a00, b00, c00), c1 = triple(a00, b10, c10);
+    const double c2 = triple(a10, b10, c11), c3 = triple(a10, b00, c01);
+    const double c4 = triple(a01, b01, c00), c5 = triple(a01, b11, c10);
+    const double c6 = triple(a11, b11, c11), c7 = triple(a11, b01, c01);
+    const double s01 = c0 + c1, s12 = c1 + c2, s23 = c2 + c3, s30 = c3 + c0;
+    const double s04 = c0 + c4, s15 = c1 + c5, s26 = c2 + c6, s37 = c3 + c7;
+    const double s45 = c4 + c5, s56 = c5 + c6, s67 = c6 + c7, s74 = c7 + c4;
+
+    // xi-edge midpoints 9, 11, 17, 19
+    const V3 B0 = add3(b00, b10), B1 = add3(b01, b11);
+    const V3 C0 = add3(c00, c10), C1 = add3(c01, c11);
+    const double d0 = triple(a00, B0, C0), d2 = triple(a10, B0, C1);
+    const double d8 = triple(a01, B1, C0), d10 = triple(a11, B1, C1);
+    double md = check_edges ? fmin(fmin(d0, d2), fmin(d8, d10)) : 0.0;
+    double me = fmin(fmin(d0 - s01, d2 - s23), fmin(d8 - s45, d10 - s67));
+    const double h02 = d0 + d2, h810 = d8 + d10, p08 = d0 + d8, p210 = d2 + d10;
+    // eta-edge midpoints 10, 12, 18, 20
+    const V3 A0 = add3(a00, a10), A1 = add3(a01, a11);
+    const V3 Cq0 = add3(c00, c01), Cq1 = add3(c10, c11);
+    const double d1 = triple(A0, b10, Cq1), d3 = triple(A0, b00, Cq0);
+    const double d9 = triple(A1, b11, Cq1), d11 = triple(A1, b01, Cq0);
+    if (check_edges) md = fmin(md, fmin(fmin(d1, d3), fmin(d9, d11)));
+    me = fmin(me, fmin(fmin(d1 - s12, d3 - s30), fmin(d9 - s56, d11 - s74)));
+    const double dz0 = h02 + (d1 + d3), dz1 = h810 + (d9 + d11);
+    const double p19 = d1 + d9, p311 = d3 + d11;
+    // zeta-edge midpoints 13..16
+    const V3 Aq0 = add3(a00, a01), Aq1 = add3(a10, a11);
+    const V3 Bq0 = add3(b00, b01), Bq1 = add3(b10, b11);
+    const double d4 = triple(Aq0, Bq0, c00), d5 = triple(Aq0, Bq1, c10);
+    const double d6 = triple(Aq1, Bq1, c11), d7 = triple(Aq1, Bq0, c01);
+    if (check_edges) md = fmin(md, fmin(fmin(d4, d5), fmin(d6, d7)));
+    me = fmin(me, fmin(fmin(d4 - s04, d5 - s15), fmin(d6 - s26, d7 - s37)));
+    const double v45 = d4 + d5, v67 = d6 + d7;
+
+    const double cz0 = s01 + s23, cz1 = s45 + s67;
+    double mf = fmin(fma(-3.0, cz0, dz0), fma(-3.0, cz1, dz1));
+    mf = fmin(mf, fmin(fma(-3.0, s01 + s45, p08 + v45), fma(-3.0, s12 + s56, p19 + (d5 + d6))));
+    mf = fmin(mf, fmin(fma(-3.0, s23 + s67, p210 + v67), fma(-3.0, s30 + s74, p311 + (d4 + d7))));
+    const double z = fma(-5.0, cz0 + cz1, (dz0 + dz1) + (v45 + v67));
+
+    const double m8 = fmin(fmin(fmin(c0, c1), fmin(c2, c3)), fmin(fmin(c4, c5), fmin(c6, c7)));
+    LeanResult r;
+    r.m20 = check_edges ? fmin(m8, 0.25 * md) : m8;
+    r.mb = fmin(fmin(0.5 * me, 0.25 * mf), 0.125 * z);
+    r.min27 = fmin(m8, r.mb);
+    r.scale = (6.0 * sx) * sy * sz;
+    r.certified_range = sx >= kScaleLo && sx <= kScaleHi && sy >= kScaleLo && sy <= kScaleHi &&
+                        sz >= kScaleLo && sz <= kScaleHi && isfinite(z);
+    return r;
+}
+
+HEXVAL_HD int lean_state(const LeanResult& r, int max_depth)
+{
+    if (!r.certified_range) return kTopExact;
+    const double tv = kTauValue * kU64 * r.scale;
+    const double tb = kTauCoeff * kU64 * r.scale;
+    if (r.m20 <= -tv) return kTopInvalid;
+    if (!(r.m20 > tv)) return kTopExact;
+    if (r.mb > tb) return kTopValid;
+    if (max_depth > 0) return kTopSubdivide;
+    return r.mb <= -tb ? kTopUndecided : kTopExact;
 }
 
 }  // namespace hexval

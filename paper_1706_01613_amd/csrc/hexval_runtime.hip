@@ -393,6 +393,9 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     if (fixed) node_cap = list_cap = 0;   // a fixed workspace keeps its capacities
     if ((rc = w.ensure(node_cap, list_cap, batched ? n_meshes : 1, batched ? n_tiles : 1))) return rc;
     QueueDev q = w.queue();
+    // a pooled workspace may be larger than this call asked for
+    if (node_cap) q.node_cap = std::min<uint64_t>(q.node_cap, node_cap);
+    if (list_cap) q.list_cap = std::min<uint64_t>(q.list_cap, list_cap);
 
     MeshDev single{};
     std::vector<MeshDev> md(n_meshes);
@@ -449,6 +452,8 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
             launch_top_list(ta, batched, list_grid, block, s);
         }
         if (timing && round == 0) HX_HIP(hipEventRecord(w.ev[1], s));
+        RootArgs ra{q, single, dmeshes};
+        launch_roots(ra, cus * 2, s);
         DrainArgs da{q, o.max_depth};
         launch_drain(da, drain_grid, s);
         FoldArgs fa{q, single, dmeshes};
