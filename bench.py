@@ -73,6 +73,103 @@ def cpu_baseline(V, C, gpu_verdicts, target_s=12.0):
             "verdict_mismatches_vs_gpu": mism}
 
 
+def fp32_leg(hx, torch, synth, steps, stream):
+    """Precision stress workload: the same lattice plus 5% near-degenerate,
+    rescaled independent hexes; plain FP64 against the FP32 filter + FP64
+    recheck on the same device-resident mesh."""
+    V, C = synth.precision_stress(seed=0, seed_extra=1)
+    pts = torch.from_numpy(V).to("cuda")
+    conn = torch.from_numpy(C).to("cuda")
+    del V, C
+    n = conn.shape[0]
+    out = {"workload": "400^3 warped lattice + 5% near-degenerate hexes (one corner within 1e-7 "
+                       "relative of flat, coordinates scaled by 10^U(-3,3))", "hexes": n}
+    res = {}
+    for name, prec in (("fp64", hx.FP64), ("fp32_filter", hx.FP32_FILTER)):
+        run_steps(hx, torch, pts, conn, 2, prec, stream)
+        wall, stats, v, m = run_steps(hx, torch, pts, conn, steps, prec, stream)
+        res[name] = (v.clone(), m.clone())
+        out[name] = {"value": n * steps / wall, "unit": "hex/s", "ms_per_step": 1e3 * wall / steps,
+                     "ms_first_pass": float(np.mean([s["ms_first_pass"] for s in stats])),
+                     "ms_recheck": float(np.mean([s["ms_recheck"] for s in stats])),
+                     "n_recheck": stats[-1]["n_recheck"], "n_exact": stats[-1]["n_exact"]}
+    out["speedup_fp32_filter"] = out["fp32_filter"]["value"] / out["fp64"]["value"]
+    out["verdicts_identical"] = bool(torch.equal(res["fp64"][0], res["fp32_filter"][0]))
+    # FP32 error of min_coeff against FP64, relative to each element's largest
+    # FP64 coefficient (elements rechecked in FP64 have error 0)
+    coeffs = hx.coefficients(pts, conn)
+    bmax = coeffs.abs().amax(dim=1)
+    del coeffs
+    err = (res["fp32_filter"][1] - res["fp64"][1]).abs() / bmax
+    err = err[torch.isfinite(err)]
+    out["fp32_min_coeff_error_vs_fp64"] = {"max": float(err.max()), "p99": float(torch.quantile(
+        err[torch.randperm(err.numel(), device=err.device)[:1 << 22]], 0.99))}
+    return out
+
+
+def serving_leg(hx, torch, synth, capacity_hex_s, n_req=2000, n_pool=32, seed=5):
+    """Poisson request streams against the server (device-resident request
+    meshes, sizes log-uniform in [1e3, 1e7] hexes, generated as in the
+    precision-stress workload), rate swept geometrically from 0.05x to 2x the
+    estimated capacity; p50/p99 latency and hexes/s per rate, FP64 and FP32
+    filter servers, plus the host-upload mode at three rates."""
+    from paper_1706_01613_amd import loadgen
+    rng = np.random.default_rng(seed)
+    sizes = np.rint(10.0 ** rng.uniform(3.0, 7.0, size=n_pool)).astype(int)
+    pool = [synth.near_degenerate_mesh_torch(int(s), seed=seed * 1000 + k) for k, s in enumerate(sizes)]
+    n_hex = np.array([C.shape[0] for _, C in pool])
+    mean = float(n_hex.mean())
+    cap_req = capacity_hex_s / mean
+    fracs = [0.05, 0.15, 0.4, 0.8, 1.2, 2.0]
+    out = {"workload": f"Poisson arrivals, {n_req} requests per rate, pool of {n_pool} device-resident "
+                       f"meshes (mean {mean:.3g} hexes, log-uniform sizes 1e3..1e7, 5% near-degenerate)",
+           "estimated_capacity_req_s": cap_req, "slots": 8}
+    idx_all = rng.integers(0, n_pool, size=n_req)
+    arena = torch.empty(loadgen.arena_bytes(n_hex[idx_all]), dtype=torch.uint8, device="cuda")
+
+    def one(server, frac, templates, n):
+        rate = frac * cap_req
+        arrival = np.cumsum(rng.exponential(1.0 / rate, size=n))
+        arrival -= arrival[0]
+        lat, st, _, wall = loadgen.run(server, arrival, idx_all[:n], templates, arena)
+        assert (st == hx.OK).all()
+        hexes = float(n_hex[idx_all[:n]].sum())
+        return {"rate_x_capacity": frac, "offered_req_s": rate, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+                "hex_s": hexes / wall, "requests": n}
+
+    dev_t = []
+    for V, C in pool:
+        r = hx.hexval_request_t()
+        r.mesh = hx.make_mesh(V, C)
+        dev_t.append(r)
+    for name, prec in (("fp64", hx.FP64), ("fp32_filter", hx.FP32_FILTER)):
+        sv = hx.hexval_server_create(hx.make_opts(precision=prec), 64 << 30, 8)
+        try:
+            one(sv, 0.5, dev_t, 200)   # warm-up (autotuning, allocations)
+            out[name] = [one(sv, f, dev_t, n_req) for f in fracs]
+        finally:
+            hx.hexval_server_destroy(sv)
+        log(f"serving {name}: " + ", ".join(f"{r['rate_x_capacity']}x p50 {r['p50_ms']:.3f} "
+                                            f"p99 {r['p99_ms']:.3f} ms" for r in out[name]))
+    # host-upload mode: meshes in pinned host memory, copied by the server
+    host = [(V.cpu().pin_memory(), C.cpu().pin_memory()) for V, C in pool]
+    host_t = []
+    for V, C in host:
+        r = hx.hexval_request_t()
+        r.mesh = hx.hexval_mesh_t(None, V.shape[0], None, C.shape[0])
+        r.host_points = V.data_ptr()
+        r.host_conn = C.data_ptr()
+        host_t.append(r)
+    sv = hx.hexval_server_create(hx.make_opts(), 64 << 30, 8)
+    try:
+        one(sv, 0.05, host_t, 100)
+        out["fp64_host_upload"] = [one(sv, f, host_t, n_req // 4) for f in (0.02, 0.05, 0.1)]
+    finally:
+        hx.hexval_server_destroy(sv)
+    return out
+
+
 def copy_calibration(torch, nbytes=1 << 30):
     """A plain device copy of known size, for scaling the profiler's
     FETCH_SIZE / WRITE_SIZE counters."""
@@ -158,6 +255,15 @@ def main():
         "call_stats": stats[-1],
         "paper_context": "about 6e6 hex/s on one core of a 2016 laptop (the paper's serial C++), context only",
     }
+    if not args.no_extras:
+        log("fp32 filter leg (precision stress workload)")
+        del pts, conn
+        torch.cuda.empty_cache()
+        out["fp32_filter_vs_fp64"] = fp32_leg(hx, torch, synth, max(5, args.steps // 2), stream)
+        log(f"fp32 leg {out['fp32_filter_vs_fp64']}")
+        torch.cuda.empty_cache()
+        log("serving leg")
+        out["serving"] = serving_leg(hx, torch, synth, value)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(V, C, v_host)

@@ -99,6 +99,9 @@ typedef struct {
     float ms_recheck;      /* device time of the FP64 recheck kernel (FP32_FILTER) */
     float ms_subdivision;  /* device time of subdivision drain + verdict fold */
     float ms_total;        /* device time from first launch to last kernel */
+    int32_t block_threads; /* first-pass block size used (tuned or given) */
+    int32_t reserved;
+    int64_t grid_blocks;   /* first-pass grid used */
 } hexval_stats_t;
 
 /* Options.  Use hexval_opts_default() and change fields. */
@@ -107,10 +110,11 @@ typedef struct {
     int32_t max_depth;        /* subdivision depth cap, 0..20, default 6 */
     int32_t validate_indices; /* nonzero: connectivity entries outside [0,n_points)
                                  give BAD_INPUT (default 0: indices are trusted) */
-    int32_t block_threads;    /* first-pass block size: 0 = tuned, else 64..1024,
+    int32_t block_threads;    /* first-pass block size: 0 = tuned, else 64..256,
                                  a multiple of 64 */
     int64_t queue_capacity;   /* subdivision queue nodes, 0 = automatic */
-    int64_t grid_blocks;      /* first-pass grid: 0 = tuned, else blocks */
+    int64_t grid_blocks;      /* first-pass grid: 0 = tuned, else blocks (rounded up
+                                 to a multiple of 8) */
     void* stream;             /* hipStream_t to run on; NULL = the null stream */
     hexval_stats_t* stats;    /* optional output */
 } hexval_opts_t;

@@ -18,6 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhexval.so")
 EMUL = os.path.join(HERE, "libhexval_emul.so")
+LOADGEN = os.path.join(HERE, "libhexval_loadgen.so")
 
 SOURCES = ["hexval_kernels.hip", "hexval_runtime.hip", "hexval_exact.cpp", "hexval_server.cpp"]
 
@@ -68,6 +69,15 @@ def build(verbose=False, jobs=4):
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         os.replace(out, EMUL)
+        # open-loop request generator for the server (benchmark/test driver)
+        out = LOADGEN + ".tmp"
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-I", INCLUDE,
+               os.path.join(CSRC, "hexval_loadgen.cpp"), "-L", HERE, "-lhexval",
+               "-Wl,-rpath,$ORIGIN", "-lpthread", "-o", out]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        os.replace(out, LOADGEN)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
     return LIB

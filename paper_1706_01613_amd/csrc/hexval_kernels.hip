@@ -45,6 +45,15 @@ __device__ __forceinline__ unsigned long long wave_reserve(unsigned long long* c
     return base + (unsigned long long)lane_rank(mask);
 }
 
+// Adds the number of lanes with `pred` to *c with one atomic per wave (every
+// lane of the wave must call this).
+__device__ __forceinline__ void wave_count(unsigned long long* c, bool pred)
+{
+    const uint64_t mask = ballot(pred);
+    if (mask && (threadIdx.x & 63) == __ffsll((unsigned long long)mask) - 1)
+        atomicAdd(c, (unsigned long long)__popcll(mask));
+}
+
 __device__ __forceinline__ uint64_t load_acquire(const uint64_t* p)
 {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -144,6 +153,7 @@ __device__ void process_element(const MeshDev& m, int mesh_idx, int64_t e, bool 
         if (bad) v = 3;
         else if (st <= kTopUndecided) v = (uint8_t)st;
     }
+    bool deferred = false;
     const bool push = active && st == kTopSubdivide;
     const uint64_t pmask = ballot(push);
     if (pmask) {
@@ -155,7 +165,7 @@ __device__ void process_element(const MeshDev& m, int mesh_idx, int64_t e, bool 
                 v = kPending;
             } else {
                 v = kDeferred;
-                atomicAdd(&q.cnt->n_deferred, 1ull);
+                deferred = true;
             }
         }
     }
@@ -170,10 +180,11 @@ __device__ void process_element(const MeshDev& m, int mesh_idx, int64_t e, bool 
                 v = kExact;
             } else {
                 v = kDeferred;
-                atomicAdd(&q.cnt->n_deferred, 1ull);
+                deferred = true;
             }
         }
     }
+    if (pmask | xmask) wave_count(&q.cnt->n_deferred, deferred);
     if (active) {
         m.verdict[e] = v;
         if (m.min_coeff) m.min_coeff[e] = bad ? __builtin_nan("") : mn;
@@ -267,6 +278,69 @@ __global__ __launch_bounds__(256) void k_top_f64_list(TopArgs a)
     }
 }
 
+// FP32 filter, one element per lane: certain INVALID / VALID elements are
+// final here (min_coeff is the FP32 minimum, widened); every other element
+// is listed for the FP64 pass (k_top_f64_list), which decides it exactly as
+// the plain FP64 path would.
+template <int G>
+__device__ void filter_element(const MeshDev& m, int mesh_idx, int64_t e, bool active, const QueueDev& q)
+{
+    V3 p[8];
+    bool bad = false;
+    int st = -1;
+    float mn = 0.0f;
+    if (active) {
+        load_points_t<G>(m, e, p, bad);
+        if (!bad) {
+            const LeanT<float> r = element_lean_t<float>(p, false);
+            st = filter_state(r);
+            mn = r.min27;
+        }
+    }
+    const bool recheck = active && !bad && st < 0;
+    uint8_t v = bad ? 3 : (uint8_t)st;
+    const uint64_t mask = ballot(recheck);
+    if (mask) {
+        const unsigned long long slot = wave_reserve(&q.cnt->n_list, mask);
+        bool deferred = false;
+        if (recheck) {
+            if (slot < q.list_cap) {
+                q.list_elem[slot] = e;
+                q.list_mesh[slot] = mesh_idx;
+                v = kPending;
+            } else {
+                v = kDeferred;
+                deferred = true;
+            }
+        }
+        wave_count(&q.cnt->n_deferred, deferred);
+    }
+    if (active) {
+        m.verdict[e] = v;
+        if (m.min_coeff && !recheck) m.min_coeff[e] = bad ? __builtin_nan("") : (double)mn;
+    }
+}
+
+template <bool BATCHED, int G>
+__global__ __launch_bounds__(256) void k_filter_f32_range(TopArgs a)
+{
+    for (TileIter it(a.n_tiles, a.xcds); it.t < it.end; it.t += it.step) {
+        MeshDev m;
+        int mi;
+        int64_t e;
+        if (BATCHED) {
+            mi = a.tile_mesh[it.t];
+            m = a.meshes[mi];
+            e = (it.t - m.tile_begin) * (int64_t)blockDim.x + threadIdx.x;
+        } else {
+            mi = 0;
+            m = a.mesh;
+            e = it.t * (int64_t)blockDim.x + threadIdx.x;
+        }
+        filter_element<G>(m, mi, e, e < m.n, a.q);
+    }
+}
+
 // ------------------------------------------------------------ subdivision
 
 __device__ __forceinline__ int mirrored(int t, int pattern)
@@ -278,6 +352,53 @@ __device__ __forceinline__ int mirrored(int t, int pattern)
     return mi + 3 * mj + 9 * mk;
 }
 
+// Claims up to 32 queued slots for the calling wave: returns the first slot
+// and sets *count (0 when nothing is queued right now).  Only slots below
+// node_tail (reserved by a producer, so written soon) are ever claimed.
+__device__ __forceinline__ unsigned long long claim_slots(Counters* cnt, uint64_t cap, int* count)
+{
+    const int lane = threadIdx.x & 63;
+    unsigned long long h = 0, n = 0;
+    if (lane == 0) {
+        for (int tries = 0; tries < 4; ++tries) {
+            h = load_relaxed(&cnt->node_head);
+            unsigned long long t = load_relaxed(&cnt->node_tail);
+            if (t > cap) t = cap;
+            if (h >= t) {
+                n = 0;
+                break;
+            }
+            n = t - h < 32 ? t - h : 32;
+            if (atomicCAS(&cnt->node_head, h, h + n) == h) break;
+            n = 0;
+        }
+    }
+    *count = (int)wave_bcast(n, 0);
+    return wave_bcast(h, 0);
+}
+
+// Watchdog of the drain: a wave that waits gives up (error flag) only when
+// the whole queue has made no progress (processed-node counter unchanged) for
+// 4 s of the 100 MHz real-time clock, so every wave is bound to exit.
+struct Watchdog {
+    unsigned long long seen = ~0ull;
+    uint64_t since = 0;
+    __device__ bool expired(Counters* cnt)
+    {
+        const int lane = threadIdx.x & 63;
+        unsigned long long now_nodes = 0;
+        if (lane == 0) now_nodes = load_relaxed(&cnt->n_nodes);
+        now_nodes = wave_bcast(now_nodes, 0);
+        const uint64_t t = __builtin_amdgcn_s_memrealtime();
+        if (now_nodes != seen) {
+            seen = now_nodes;
+            since = t;
+            return false;
+        }
+        return t - since > 400000000ull;
+    }
+};
+
 __global__ __launch_bounds__(256) void k_drain(DrainArgs a)
 {
     const int lane = threadIdx.x & 63;
@@ -286,98 +407,106 @@ __global__ __launch_bounds__(256) void k_drain(DrainArgs a)
     const QueueDev& q = a.q;
     Counters* cnt = q.cnt;
     const uint64_t cap = q.node_cap;
-    uint64_t idle_since = __builtin_amdgcn_s_memrealtime();
+    Watchdog dog;
     for (;;) {
-        unsigned long long h = 0;
-        if (lane == 0) h = atomicAdd(&cnt->node_head, 8ull);
-        h = wave_bcast(h, 0);
-        if (h >= cap) return;
-        const uint64_t slot = h + grp;
-        bool pending = slot < cap;
+        int n = 0;
+        const unsigned long long h = claim_slots(cnt, cap, &n);
+        if (n == 0) {
+            unsigned long long out = 0;
+            if (lane == 0) out = load_relaxed(&cnt->outstanding);
+            out = wave_bcast(out, 0);
+            if (out == 0) return;
+            __builtin_amdgcn_s_sleep(1);
+            if (dog.expired(cnt)) {
+                if (lane == 0) atomicOr(&cnt->error, kErrSpinTimeout);
+                return;
+            }
+            continue;
+        }
+        for (int sub = 0; sub < n; sub += 8) {
+        const uint64_t slot = h + sub + grp;
+        bool pending = sub + grp < n;
         while (ballot(pending)) {
             // Poll with relaxed loads (no cache maintenance per poll); one
             // acquire fence once a node is seen complete.
             const bool ready = pending && load_relaxed64(&q.nodes[slot].ready) == q.epoch;
             const uint64_t rmask = ballot(ready);
-            if (rmask) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                // ---- one child of a ready node per lane
-                bool push = false, invalid = false, undecided = false, inexact = false;
-                double t[27];
-                int level = 0;
-                int64_t sslot = 0;
-                double scale = 0.0;
-                if (ready) {
-                    const Node* nd = q.nodes + slot;
-                    const int pat = nd->orient ^ child;
-                    level = nd->level + 1;
-                    sslot = nd->slot;
-                    scale = nd->scale;
-#pragma unroll
-                    for (int k = 0; k < 27; ++k) t[k] = nd->b[mirrored(k, pat)];
-                    const bool dead =
-                        (__hip_atomic_load(q.sub_flags + sslot, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT) & kFlagInvalid) != 0u;
-                    if (!dead) {
-                        lower_octant(t);
-                        const double tau = level_threshold(scale, level);
-                        const double m8 = fmin(fmin(fmin(t[0], t[2]), fmin(t[6], t[8])),
-                                               fmin(fmin(t[18], t[20]), fmin(t[24], t[26])));
-                        double m19 = t[1];
-#pragma unroll
-                        for (int k = 3; k < 26; ++k)
-                            if (k != 6 && k != 8 && k != 18 && k != 20 && k != 24) m19 = fmin(m19, t[k]);
-                        if (m8 <= -tau) invalid = true;
-                        else if (!(m8 > tau)) inexact = true;
-                        else if (m19 > tau) { /* positive on this sub-box */ }
-                        else if (level < a.max_depth) push = true;
-                        else if (m19 <= -tau) undecided = true;
-                        else inexact = true;
-                    }
+            if (!rmask) {
+                __builtin_amdgcn_s_sleep(1);
+                if (dog.expired(cnt)) {
+                    if (lane == 0) atomicOr(&cnt->error, kErrSpinTimeout);
+                    return;
                 }
-                const uint32_t fl = (invalid ? kFlagInvalid : 0u) | (undecided ? kFlagUndecided : 0u) |
-                                    (inexact ? kFlagExact : 0u);
-                const uint64_t pmask = ballot(push);
-                if (pmask) {
-                    const unsigned long long ns = wave_reserve(&cnt->node_tail, pmask);
-                    const bool stored = push && ns < cap;
-                    const uint64_t smask = ballot(stored);
-                    if (smask && lane == __ffsll((unsigned long long)pmask) - 1)
-                        atomicAdd(&cnt->outstanding, (unsigned long long)__popcll(smask));
-                    if (stored) {
-                        Node* out = q.nodes + ns;
-#pragma unroll
-                        for (int k = 0; k < 27; ++k) out->b[k] = t[k];
-                        out->scale = scale;
-                        out->slot = sslot;
-                        out->level = level;
-                        out->orient = child;
-                        store_release(&out->ready, q.epoch);
-                    } else if (push) {
-                        atomicOr(q.sub_flags + sslot, kFlagOverflow);
-                    }
-                }
-                if (fl) atomicOr(q.sub_flags + sslot, fl);
-                if (lane == 0) {
-                    const unsigned int nproc = (unsigned int)(__popcll(rmask) / 8);
-                    atomicAdd(&cnt->n_nodes, (unsigned long long)__popcll(rmask));
-                    atomicSub(&cnt->outstanding, (unsigned long long)nproc);
-                }
-                if (ready) atomicMax(&cnt->max_level, (unsigned int)level);
-                pending = pending && !ready;
-                idle_since = __builtin_amdgcn_s_memrealtime();
                 continue;
             }
-            unsigned long long out = 0;
-            if (lane == 0) out = load_relaxed(&cnt->outstanding);
-            out = wave_bcast(out, 0);
-            if (out == 0) return;
-            __builtin_amdgcn_s_sleep(2);
-            // 100 MHz real-time clock: give up after 4 s without progress.
-            if (__builtin_amdgcn_s_memrealtime() - idle_since > 400000000ull) {
-                if (lane == 0) atomicOr(&cnt->error, kErrSpinTimeout);
-                return;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            // ---- one child of a ready node per lane
+            bool push = false, invalid = false, undecided = false, inexact = false;
+            double t[27];
+            int level = 0;
+            int64_t sslot = 0;
+            double scale = 0.0;
+            if (ready) {
+                const Node* nd = q.nodes + slot;
+                const int pat = nd->orient ^ child;
+                level = nd->level + 1;
+                sslot = nd->slot;
+                scale = nd->scale;
+#pragma unroll
+                for (int k = 0; k < 27; ++k) t[k] = nd->b[mirrored(k, pat)];
+                const bool dead = (__hip_atomic_load(q.sub_flags + sslot, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT) & kFlagInvalid) != 0u;
+                if (!dead) {
+                    lower_octant(t);
+                    const double tau = level_threshold(scale, level);
+                    const double m8 = fmin(fmin(fmin(t[0], t[2]), fmin(t[6], t[8])),
+                                           fmin(fmin(t[18], t[20]), fmin(t[24], t[26])));
+                    double m19 = t[1];
+#pragma unroll
+                    for (int k = 3; k < 26; ++k)
+                        if (k != 6 && k != 8 && k != 18 && k != 20 && k != 24) m19 = fmin(m19, t[k]);
+                    if (m8 <= -tau) invalid = true;
+                    else if (!(m8 > tau)) inexact = true;
+                    else if (m19 > tau) { /* positive on this sub-box */ }
+                    else if (level < a.max_depth) push = true;
+                    else if (m19 <= -tau) undecided = true;
+                    else inexact = true;
+                }
             }
+            const uint32_t fl = (invalid ? kFlagInvalid : 0u) | (undecided ? kFlagUndecided : 0u) |
+                                (inexact ? kFlagExact : 0u);
+            const uint64_t pmask = ballot(push);
+            if (pmask) {
+                const unsigned long long ns = wave_reserve(&cnt->node_tail, pmask);
+                const bool stored = push && ns < cap;
+                const uint64_t smask = ballot(stored);
+                if (smask && lane == __ffsll((unsigned long long)pmask) - 1)
+                    atomicAdd(&cnt->outstanding, (unsigned long long)__popcll(smask));
+                if (stored) {
+                    Node* out = q.nodes + ns;
+#pragma unroll
+                    for (int k = 0; k < 27; ++k) out->b[k] = t[k];
+                    out->scale = scale;
+                    out->slot = sslot;
+                    out->level = level;
+                    out->orient = child;
+                    store_release(&out->ready, q.epoch);
+                } else if (push) {
+                    atomicOr(q.sub_flags + sslot, kFlagOverflow);
+                }
+            }
+            if (fl) atomicOr(q.sub_flags + sslot, fl);
+            // one atomic per counter and wave
+            int lv = ready ? level : 0;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) lv = max(lv, __shfl_xor(lv, d, 64));
+            if (lane == 0) {
+                atomicAdd(&cnt->n_nodes, (unsigned long long)__popcll(rmask));
+                atomicSub(&cnt->outstanding, (unsigned long long)(__popcll(rmask) / 8));
+                atomicMax(&cnt->max_level, (unsigned int)lv);
+            }
+            pending = pending && !ready;
+        }
         }
     }
 }
@@ -387,35 +516,43 @@ __global__ __launch_bounds__(256) void k_fold(FoldArgs a)
     const QueueDev& q = a.q;
     const unsigned long long ns = *(&q.cnt->n_sub);
     const int64_t n = (int64_t)(ns < q.node_cap ? ns : q.node_cap);
-    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e = q.sub_elem[s];
-        if (e < 0) continue;
-        const uint32_t f = q.sub_flags[s];
-        const int mi = q.sub_mesh[s];
-        const MeshDev m = a.meshes ? a.meshes[mi] : a.mesh;
-        uint8_t v;
-        if (f & kFlagInvalid) {
-            v = 0;
-        } else if (f & kFlagExact) {
-            const unsigned long long x = atomicAdd(&q.cnt->n_exact, 1ull);
-            if (x < q.exact_cap) {
-                q.exact_elem[x] = e;
-                q.exact_mesh[x] = mi;
-                v = kExact;
-            } else {
-                v = kDeferred;
-                atomicAdd(&q.cnt->n_deferred, 1ull);
-            }
-        } else if (f & kFlagOverflow) {
-            v = kDeferred;
-            atomicAdd(&q.cnt->n_deferred, 1ull);
-        } else if (f & kFlagUndecided) {
-            v = 2;
-        } else {
-            v = 1;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // whole waves iterate together (wave-level list appends and counters)
+    for (int64_t s0 = blockIdx.x * (int64_t)blockDim.x; s0 < n; s0 += stride) {
+        const int64_t s = s0 + threadIdx.x;
+        const bool active = s < n;
+        uint32_t f = 0;
+        int64_t e = -1;
+        int mi = 0;
+        if (active) {
+            e = q.sub_elem[s];
+            f = q.sub_flags[s];
+            mi = q.sub_mesh[s];
         }
-        m.verdict[e] = v;
+        const bool live = active && e >= 0;
+        const bool to_exact = live && !(f & kFlagInvalid) && (f & kFlagExact);
+        bool deferred = live && !(f & kFlagInvalid) && !(f & kFlagExact) && (f & kFlagOverflow);
+        uint8_t v = (f & kFlagInvalid) ? 0 : (f & kFlagUndecided) ? 2 : 1;
+        if (deferred) v = kDeferred;
+        const uint64_t xmask = ballot(to_exact);
+        if (xmask) {
+            const unsigned long long x = wave_reserve(&q.cnt->n_exact, xmask);
+            if (to_exact) {
+                if (x < q.exact_cap) {
+                    q.exact_elem[x] = e;
+                    q.exact_mesh[x] = mi;
+                    v = kExact;
+                } else {
+                    v = kDeferred;
+                    deferred = true;
+                }
+            }
+        }
+        wave_count(&q.cnt->n_deferred, deferred);
+        if (live) {
+            const MeshDev m = a.meshes ? a.meshes[mi] : a.mesh;
+            m.verdict[e] = v;
+        }
     }
 }
 
@@ -528,6 +665,17 @@ void launch_top_range(const TopArgs& a, bool batched, int grid, int block, hipSt
         else HX_TOP(false, kGatherChecked);
     }
 #undef HX_TOP
+}
+
+void launch_filter_range(const TopArgs& a, bool batched, int grid, int block, hipStream_t s)
+{
+    if (batched) {
+        HX_LAUNCH((k_filter_f32_range<true, kGatherAny>), grid, block, s, a);
+        return;
+    }
+    if (!a.mesh.conn) HX_LAUNCH((k_filter_f32_range<false, kGatherPoints>), grid, block, s, a);
+    else if (a.mesh.validate) HX_LAUNCH((k_filter_f32_range<false, kGatherChecked>), grid, block, s, a);
+    else HX_LAUNCH((k_filter_f32_range<false, kGatherConn>), grid, block, s, a);
 }
 
 void launch_top_list(const TopArgs& a, bool batched, int grid, int block, hipStream_t s)

@@ -59,6 +59,7 @@ struct ScatterArgs {
 };
 
 void launch_top_range(const TopArgs& a, bool batched, int grid, int block, hipStream_t s);
+void launch_filter_range(const TopArgs& a, bool batched, int grid, int block, hipStream_t s);
 void launch_top_list(const TopArgs& a, bool batched, int grid, int block, hipStream_t s);
 void launch_drain(const DrainArgs& a, int grid, hipStream_t s);
 void launch_roots(const RootArgs& a, int grid, hipStream_t s);

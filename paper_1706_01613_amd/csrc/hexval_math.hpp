@@ -274,76 +274,145 @@ namespace hexval {
 // The first-pass quantities only (no coefficient array): the same operations
 // and roundings as element_values + summarize, ordered so that the edge
 // values are consumed as soon as they are formed (fewer live registers).
-struct LeanResult {
-    double m20, mb, min27, scale;
+// T = double is the FP64 pass; T = float is the FP32 filter, whose edge
+// vectors are formed in FP64 and rounded once to FP32 (everything after that
+// in FP32 with the same operation order).
+template <typename T>
+struct LeanT {
+    T m20, mb, min27, scale;
     bool certified_range;
+};
+using LeanResult = LeanT<double>;
+
+template <typename T>
+struct W3 {
+    T x, y, z;
+};
+
+template <typename T>
+HEXVAL_HD W3<T> edge_t(V3 a, V3 b)
+{
+    return {(T)(a.x - b.x), (T)(a.y - b.y), (T)(a.z - b.z)};
+}
+
+template <typename T>
+HEXVAL_HD W3<T> add_t(W3<T> a, W3<T> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+
+template <typename T>
+HEXVAL_HD T triple_t(W3<T> a, W3<T> b, W3<T> c)
+{
+    const T x = fma(b.y, c.z, -(b.z * c.y));
+    const T y = fma(b.z, c.x, -(b.x * c.z));
+    const T z = fma(b.x, c.y, -(b.y * c.x));
+    return fma(a.z, z, fma(a.y, y, a.x * x));
+}
+
+template <typename T>
+HEXVAL_HD T amax_t(T m, W3<T> v)
+{
+    return fmax(m, fmax(fabs(v.x), fmax(fabs(v.y), fabs(v.z))));
+}
+
+// Scale guard per precision: every per-direction scale inside [lo, hi].
+template <typename T> struct Guard;
+template <> struct Guard<double> {
+    static constexpr double lo = 0x1p-300, hi = 0x1p+300;
+};
+template <> struct Guard<float> {
+    static constexpr float lo = 0x1p-30f, hi = 0x1p+30f;
 };
 
 // check_edges: also test the 12 edge-midpoint values in the step-2 minimum.
 // Without it an element whose only non-positive value sits at an edge
 // midpoint is sent to subdivision, where that midpoint is a corner of a
 // level-1 sub-box, so the verdict is the same whenever the depth cap is >= 1.
-HEXVAL_HD LeanResult element_lean(const V3 p[8], bool check_edges)
+template <typename T>
+HEXVAL_HD LeanT<T> element_lean_t(const V3 p[8], bool check_edges)
 {
-    const V3 a00 = sub3(p[1], p[0]), a10 = sub3(p[2], p[3]);
-    const V3 a01 = sub3(p[5], p[4]), a11 = sub3(p[6], p[7]);
-    const V3 b00 = sub3(p[3], p[0]), b10 = sub3(p[2], p[1]);
-    const V3 b01 = sub3(p[7], p[4]), b11 = sub3(p[6], p[5]);
-    const V3 c00 = sub3(p[4], p[0]), c10 = sub3(p[5], p[1]);
-    const V3 c01 = sub3(p[7], p[3]), c11 = sub3(p[6], p[2]);
-    const double sx = fmax(fmax(amax(fabs(a00.x), a10), amax(fabs(a00.y), a01)), amax(fabs(a00.z), a11));
-    const double sy = fmax(fmax(amax(fabs(b00.x), b10), amax(fabs(b00.y), b01)), amax(fabs(b00.z), b11));
-    const double sz = fmax(fmax(amax(fabs(c00.x), c10), amax(fabs(c00.y), c01)), amax(fabs(c00.z), c11));
+    const W3<T> a00 = edge_t<T>(p[1], p[0]), a10 = edge_t<T>(p[2], p[3]);
+    const W3<T> a01 = edge_t<T>(p[5], p[4]), a11 = edge_t<T>(p[6], p[7]);
+    const W3<T> b00 = edge_t<T>(p[3], p[0]), b10 = edge_t<T>(p[2], p[1]);
+    const W3<T> b01 = edge_t<T>(p[7], p[4]), b11 = edge_t<T>(p[6], p[5]);
+    const W3<T> c00 = edge_t<T>(p[4], p[0]), c10 = edge_t<T>(p[5], p[1]);
+    const W3<T> c01 = edge_t<T>(p[7], p[3]), c11 = edge_t<T>(p[6], p[2]);
+    const T sx = fmax(fmax(amax_t(fabs(a00.x), a10), amax_t(fabs(a00.y), a01)), amax_t(fabs(a00.z), a11));
+    const T sy = fmax(fmax(amax_t(fabs(b00.x), b10), amax_t(fabs(b00.y), b01)), amax_t(fabs(b00.z), b11));
+    const T sz = fmax(fmax(amax_t(fabs(c00.x), c10), amax_t(fabs(c00.y), c01)), amax_t(fabs(c00.z), c11));
 
-    const double c0 = triple(a00, b00, c00), c1 = triple(a00, b10, c10);
-    const double c2 = triple(a10, b10, c11), c3 = triple(a10, b00, c01);
-    const double c4 = triple(a01, b01, c00), c5 = triple(a01, b11, c10);
-    const double c6 = triple(a11, b11, c11), c7 = triple(a11, b01, c01);
-    const double s01 = c0 + c1, s12 = c1 + c2, s23 = c2 + c3, s30 = c3 + c0;
-    const double s04 = c0 + c4, s15 = c1 + c5, s26 = c2 + c6, s37 = c3 + c7;
-    const double s45 = c4 + c5, s56 = c5 + c6, s67 = c6 + c7, s74 = c7 + c4;
+    const T c0 = triple_t(a00, b00, c00), c1 = triple_t(a00, b10, c10);
+    const T c2 = triple_t(a10, b10, c11), c3 = triple_t(a10, b00, c01);
+    const T c4 = triple_t(a01, b01, c00), c5 = triple_t(a01, b11, c10);
+    const T c6 = triple_t(a11, b11, c11), c7 = triple_t(a11, b01, c01);
+    const T s01 = c0 + c1, s12 = c1 + c2, s23 = c2 + c3, s30 = c3 + c0;
+    const T s04 = c0 + c4, s15 = c1 + c5, s26 = c2 + c6, s37 = c3 + c7;
+    const T s45 = c4 + c5, s56 = c5 + c6, s67 = c6 + c7, s74 = c7 + c4;
 
     // xi-edge midpoints 9, 11, 17, 19
-    const V3 B0 = add3(b00, b10), B1 = add3(b01, b11);
-    const V3 C0 = add3(c00, c10), C1 = add3(c01, c11);
-    const double d0 = triple(a00, B0, C0), d2 = triple(a10, B0, C1);
-    const double d8 = triple(a01, B1, C0), d10 = triple(a11, B1, C1);
-    double md = check_edges ? fmin(fmin(d0, d2), fmin(d8, d10)) : 0.0;
-    double me = fmin(fmin(d0 - s01, d2 - s23), fmin(d8 - s45, d10 - s67));
-    const double h02 = d0 + d2, h810 = d8 + d10, p08 = d0 + d8, p210 = d2 + d10;
+    const W3<T> B0 = add_t(b00, b10), B1 = add_t(b01, b11);
+    const W3<T> C0 = add_t(c00, c10), C1 = add_t(c01, c11);
+    const T d0 = triple_t(a00, B0, C0), d2 = triple_t(a10, B0, C1);
+    const T d8 = triple_t(a01, B1, C0), d10 = triple_t(a11, B1, C1);
+    T md = check_edges ? fmin(fmin(d0, d2), fmin(d8, d10)) : T(0);
+    T me = fmin(fmin(d0 - s01, d2 - s23), fmin(d8 - s45, d10 - s67));
+    const T h02 = d0 + d2, h810 = d8 + d10, p08 = d0 + d8, p210 = d2 + d10;
     // eta-edge midpoints 10, 12, 18, 20
-    const V3 A0 = add3(a00, a10), A1 = add3(a01, a11);
-    const V3 Cq0 = add3(c00, c01), Cq1 = add3(c10, c11);
-    const double d1 = triple(A0, b10, Cq1), d3 = triple(A0, b00, Cq0);
-    const double d9 = triple(A1, b11, Cq1), d11 = triple(A1, b01, Cq0);
+    const W3<T> A0 = add_t(a00, a10), A1 = add_t(a01, a11);
+    const W3<T> Cq0 = add_t(c00, c01), Cq1 = add_t(c10, c11);
+    const T d1 = triple_t(A0, b10, Cq1), d3 = triple_t(A0, b00, Cq0);
+    const T d9 = triple_t(A1, b11, Cq1), d11 = triple_t(A1, b01, Cq0);
     if (check_edges) md = fmin(md, fmin(fmin(d1, d3), fmin(d9, d11)));
     me = fmin(me, fmin(fmin(d1 - s12, d3 - s30), fmin(d9 - s56, d11 - s74)));
-    const double dz0 = h02 + (d1 + d3), dz1 = h810 + (d9 + d11);
-    const double p19 = d1 + d9, p311 = d3 + d11;
+    const T dz0 = h02 + (d1 + d3), dz1 = h810 + (d9 + d11);
+    const T p19 = d1 + d9, p311 = d3 + d11;
     // zeta-edge midpoints 13..16
-    const V3 Aq0 = add3(a00, a01), Aq1 = add3(a10, a11);
-    const V3 Bq0 = add3(b00, b01), Bq1 = add3(b10, b11);
-    const double d4 = triple(Aq0, Bq0, c00), d5 = triple(Aq0, Bq1, c10);
-    const double d6 = triple(Aq1, Bq1, c11), d7 = triple(Aq1, Bq0, c01);
+    const W3<T> Aq0 = add_t(a00, a01), Aq1 = add_t(a10, a11);
+    const W3<T> Bq0 = add_t(b00, b01), Bq1 = add_t(b10, b11);
+    const T d4 = triple_t(Aq0, Bq0, c00), d5 = triple_t(Aq0, Bq1, c10);
+    const T d6 = triple_t(Aq1, Bq1, c11), d7 = triple_t(Aq1, Bq0, c01);
     if (check_edges) md = fmin(md, fmin(fmin(d4, d5), fmin(d6, d7)));
     me = fmin(me, fmin(fmin(d4 - s04, d5 - s15), fmin(d6 - s26, d7 - s37)));
-    const double v45 = d4 + d5, v67 = d6 + d7;
+    const T v45 = d4 + d5, v67 = d6 + d7;
 
-    const double cz0 = s01 + s23, cz1 = s45 + s67;
-    double mf = fmin(fma(-3.0, cz0, dz0), fma(-3.0, cz1, dz1));
-    mf = fmin(mf, fmin(fma(-3.0, s01 + s45, p08 + v45), fma(-3.0, s12 + s56, p19 + (d5 + d6))));
-    mf = fmin(mf, fmin(fma(-3.0, s23 + s67, p210 + v67), fma(-3.0, s30 + s74, p311 + (d4 + d7))));
-    const double z = fma(-5.0, cz0 + cz1, (dz0 + dz1) + (v45 + v67));
+    const T cz0 = s01 + s23, cz1 = s45 + s67;
+    T mf = fmin(fma(T(-3), cz0, dz0), fma(T(-3), cz1, dz1));
+    mf = fmin(mf, fmin(fma(T(-3), s01 + s45, p08 + v45), fma(T(-3), s12 + s56, p19 + (d5 + d6))));
+    mf = fmin(mf, fmin(fma(T(-3), s23 + s67, p210 + v67), fma(T(-3), s30 + s74, p311 + (d4 + d7))));
+    const T z = fma(T(-5), cz0 + cz1, (dz0 + dz1) + (v45 + v67));
 
-    const double m8 = fmin(fmin(fmin(c0, c1), fmin(c2, c3)), fmin(fmin(c4, c5), fmin(c6, c7)));
-    LeanResult r;
-    r.m20 = check_edges ? fmin(m8, 0.25 * md) : m8;
-    r.mb = fmin(fmin(0.5 * me, 0.25 * mf), 0.125 * z);
+    const T m8 = fmin(fmin(fmin(c0, c1), fmin(c2, c3)), fmin(fmin(c4, c5), fmin(c6, c7)));
+    LeanT<T> r;
+    r.m20 = check_edges ? fmin(m8, T(0.25) * md) : m8;
+    r.mb = fmin(fmin(T(0.5) * me, T(0.25) * mf), T(0.125) * z);
     r.min27 = fmin(m8, r.mb);
-    r.scale = (6.0 * sx) * sy * sz;
-    r.certified_range = sx >= kScaleLo && sx <= kScaleHi && sy >= kScaleLo && sy <= kScaleHi &&
-                        sz >= kScaleLo && sz <= kScaleHi && isfinite(z);
+    r.scale = (T(6) * sx) * sy * sz;
+    r.certified_range = sx >= Guard<T>::lo && sx <= Guard<T>::hi && sy >= Guard<T>::lo &&
+                        sy <= Guard<T>::hi && sz >= Guard<T>::lo && sz <= Guard<T>::hi && isfinite(z);
     return r;
+}
+
+HEXVAL_HD LeanResult element_lean(const V3 p[8], bool check_edges)
+{
+    return element_lean_t<double>(p, check_edges);
+}
+
+// FP32 filter thresholds, in units of u32 M^ (u32 = 2^-24).  Each edge
+// component carries one FP64 and one FP32 rounding (relative u32 (1 + 2^-29));
+// everything after follows the FP64 derivation with u -> u32, whose
+// multipliers (8.01, 40.01, 32.01, 85.01, 150.02) keep their slack at this
+// precision (second-order terms are below 1e-5 of the first).  The FP32
+// values of the guard keep all products in the normal range with a margin
+// far above the underflow error.
+constexpr float kU32 = 5.9604644775390625e-08f;   // 2^-24
+
+// Outcome of the FP32 pass: 0 INVALID, 1 VALID (both certain), -1 recheck in FP64.
+HEXVAL_HD int filter_state(const LeanT<float>& r)
+{
+    if (!r.certified_range) return -1;
+    const float tv = kTauValue * kU32 * r.scale;
+    const float tb = kTauCoeff * kU32 * r.scale;
+    if (r.m20 <= -tv) return kTopInvalid;
+    if (r.m20 > tv && r.mb > tb) return kTopValid;
+    return -1;
 }
 
 HEXVAL_HD int lean_state(const LeanResult& r, int max_depth)

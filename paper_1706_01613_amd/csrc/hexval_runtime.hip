@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -77,6 +78,12 @@ int current_device(int* dev, int* cus)
     *dev = d;
     if (cus) *cus = di.cus;
     return HEXVAL_OK;
+}
+
+const char* device_arch(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    return g_dev[dev].arch;
 }
 
 // ---------------------------------------------------------------- workspace
@@ -332,6 +339,75 @@ static void run_exact_host(const double* pts, uint8_t* out, int64_t n, int max_d
     for (auto& x : th) x.join();
 }
 
+// ---------------------------------------------------------------- autotuner
+// Launch shape of the first-pass kernel: threads per block (= elements per
+// tile) and grid (one tile per block, or a persistent grid of k blocks per
+// CU striding over the tiles).  Picked by timing every candidate once on the
+// call's own input (after one untimed run), cached per (device architecture,
+// precision, gather mode, batched, log2 size bucket) and optionally
+// persisted in the file named by HEXVAL_TUNE_CACHE.  The per-element
+// arithmetic never depends on the launch shape.
+
+struct TuneChoice {
+    int block = 256;
+    int per_cu = 0;   // 0: one tile per block; k: persistent grid of k blocks per CU
+};
+
+static std::mutex g_tune_mu;
+static std::map<std::string, TuneChoice> g_tune;
+static bool g_tune_loaded = false;
+
+static std::string tune_key(const char* arch, int precision, int gather, bool batched, int64_t total)
+{
+    int bucket = 0;
+    while ((1ll << (bucket + 1)) <= total) ++bucket;
+    char buf[128];
+    snprintf(buf, sizeof buf, "%s/p%d/g%d/b%d/n%d", arch, precision, gather, batched ? 1 : 0, bucket);
+    return buf;
+}
+
+static void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = getenv("HEXVAL_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char key[128];
+    int block, per_cu;
+    while (fscanf(f, "%127s %d %d", key, &block, &per_cu) == 3) {
+        TuneChoice c;
+        c.block = block;
+        c.per_cu = per_cu;
+        g_tune[key] = c;
+    }
+    fclose(f);
+}
+
+static void tune_store_locked(const std::string& key, const TuneChoice& c)
+{
+    g_tune[key] = c;
+    const char* path = getenv("HEXVAL_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d\n", key.c_str(), c.block, c.per_cu);
+    fclose(f);
+}
+
+static int64_t grid_for(const TuneChoice& c, int64_t n_tiles, int cus)
+{
+    int64_t g = c.per_cu ? std::min<int64_t>(n_tiles, (int64_t)cus * c.per_cu) : n_tiles;
+    return std::min<int64_t>(std::max<int64_t>(8, (g + 7) / 8 * 8), 1ll << 30);
+}
+
+bool autotune_enabled()
+{
+    const char* e = getenv("HEXVAL_AUTOTUNE");
+    return !(e && e[0] == '0');
+}
+
 // ---------------------------------------------------------------- main loop
 
 int run_check(const hexval_mesh_t* meshes, int n_meshes, bool batched, const hexval_opts_t* opts,
@@ -367,7 +443,23 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     if ((rc = current_device(&dev, &cus))) return rc;
     hipStream_t s = (hipStream_t)o.stream;
 
-    const int block = o.block_threads ? o.block_threads : 256;
+    // Launch shape of the first pass: explicit options, else the tuning cache,
+    // else (autotuning on) measured below on this input, else defaults.
+    TuneChoice choice;
+    choice.per_cu = batched ? 8 : 0;
+    const int gather = batched ? 0 : !meshes[0].connectivity ? 1 : (o.validate_indices ? 3 : 2);
+    std::string key;
+    bool need_tune = false;
+    if (o.block_threads || o.grid_blocks) {
+        if (o.block_threads) choice.block = o.block_threads;
+    } else {
+        key = tune_key(device_arch(dev), o.precision, gather, batched, total);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) choice = it->second;
+        else need_tune = autotune_enabled();
+    }
     // Automatic queue size: 1/32 of the elements, at least 2^19 nodes (any
     // single element's tree at the default cap fits), and room for a tree
     // whose ambiguous region is a surface (4^level live sub-boxes) at the
@@ -379,19 +471,18 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     uint64_t list_cap = o.precision == HEXVAL_FP32_FILTER
                             ? pow2_ceil(std::min<uint64_t>(std::max<uint64_t>(total / 8, 1u << 16), 1u << 27))
                             : std::max<uint64_t>(node_cap, 1u << 16);
-    // tiles
-    std::vector<int64_t> tile_begin(n_meshes);
-    int64_t n_tiles = 0;
-    for (int i = 0; i < n_meshes; ++i) {
-        tile_begin[i] = n_tiles;
-        n_tiles += (meshes[i].n + block - 1) / block;
-    }
+    auto count_tiles = [&](int blk) {
+        int64_t t = 0;
+        for (int i = 0; i < n_meshes; ++i) t += (meshes[i].n + blk - 1) / blk;
+        return t;
+    };
 
     WorkspaceGuard wg;
     if (!fixed && (rc = acquire_workspace(dev, &wg.w))) return rc;
     Workspace& w = fixed ? *fixed : *wg.w;
     if (fixed) node_cap = list_cap = 0;   // a fixed workspace keeps its capacities
-    if ((rc = w.ensure(node_cap, list_cap, batched ? n_meshes : 1, batched ? n_tiles : 1))) return rc;
+    const int64_t max_tiles = count_tiles(need_tune ? 64 : choice.block);
+    if ((rc = w.ensure(node_cap, list_cap, batched ? n_meshes : 1, batched ? max_tiles : 1))) return rc;
     QueueDev q = w.queue();
     // a pooled workspace may be larger than this call asked for
     if (node_cap) q.node_cap = std::min<uint64_t>(q.node_cap, node_cap);
@@ -407,33 +498,31 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         m.n_points = meshes[i].n_points;
         m.verdict = verdicts[i];
         m.min_coeff = mins ? mins[i] : nullptr;
-        m.tile_begin = tile_begin[i];
         m.validate = (o.validate_indices && m.conn) ? 1 : 0;
     }
-    const MeshDev* dmeshes = nullptr;
-    if (batched) {
-        memcpy(w.h_meshes, md.data(), n_meshes * sizeof(MeshDev));
-        HX_HIP(hipMemcpyAsync(w.meshes, w.h_meshes, n_meshes * sizeof(MeshDev), hipMemcpyHostToDevice, s));
-        launch_tile_table(w.meshes, n_meshes, block, w.tile_mesh, s);
-        dmeshes = w.meshes;
-    } else {
-        single = md[0];
-    }
-
+    const MeshDev* dmeshes = batched ? w.meshes : nullptr;
+    int64_t n_tiles = 0;
+    // Tiles of `blk` elements; for a batch the mesh table and the
+    // tile -> mesh table are rebuilt on the device.
+    auto setup_tiles = [&](int blk) -> int {
+        n_tiles = 0;
+        for (int i = 0; i < n_meshes; ++i) {
+            md[i].tile_begin = n_tiles;
+            n_tiles += (meshes[i].n + blk - 1) / blk;
+        }
+        if (batched) {
+            HX_HIP(hipStreamSynchronize(s));   // h_meshes may still be in use
+            memcpy(w.h_meshes, md.data(), n_meshes * sizeof(MeshDev));
+            HX_HIP(hipMemcpyAsync(w.meshes, w.h_meshes, n_meshes * sizeof(MeshDev), hipMemcpyHostToDevice, s));
+            launch_tile_table(w.meshes, n_meshes, blk, w.tile_mesh, s);
+        } else {
+            single = md[0];
+        }
+        return HEXVAL_OK;
+    };
     const bool timing = st && st->timing;
     const int xcds = 8;
-    int64_t grid = o.grid_blocks;
-    if (!grid) grid = batched ? std::min<int64_t>(n_tiles, (int64_t)cus * 8) : n_tiles;
-    grid = std::max<int64_t>(xcds, (grid + xcds - 1) / xcds * xcds);
-    grid = std::min<int64_t>(grid, (1ll << 30));
-    const int list_grid = cus * 8;
-    const int drain_grid = cus;
-
-    uint64_t prev_remaining = 0;
-    for (int round = 0;; ++round) {
-        ++w.epoch;
-        q.epoch = w.epoch;
-        launch_reset(w.cnt, s);
+    auto first_args = [&]() {
         TopArgs ta{};
         ta.mesh = single;
         ta.meshes = dmeshes;
@@ -443,8 +532,66 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         ta.q = q;
         ta.max_depth = o.max_depth;
         ta.xcds = xcds;
+        return ta;
+    };
+    auto launch_first = [&](const TopArgs& ta, int64_t g, int blk) {
+        if (o.precision == HEXVAL_FP32_FILTER) launch_filter_range(ta, batched, (int)g, blk, s);
+        else launch_top_range(ta, batched, (int)g, blk, s);
+    };
+    if (need_tune) {
+        static const int kBlocks[3] = {64, 128, 256};
+        static const int kSingle[4] = {0, 4, 8, 16}, kBatched[4] = {4, 8, 16, 32};
+        float best = 1e30f;
+        for (int blk : kBlocks) {
+            if ((rc = setup_tiles(blk))) return rc;
+            for (int k = 0; k < 4; ++k) {
+                TuneChoice c;
+                c.block = blk;
+                c.per_cu = batched ? kBatched[k] : kSingle[k];
+                const int64_t g = grid_for(c, n_tiles, cus);
+                float ms = 0.0f;
+                for (int rep = 0; rep < 2; ++rep) {
+                    launch_reset(w.cnt, s);
+                    HX_HIP(hipEventRecord(w.ev[0], s));
+                    launch_first(first_args(), g, blk);
+                    HX_HIP(hipEventRecord(w.ev[1], s));
+                    HX_HIP(hipGetLastError());
+                    HX_HIP(hipEventSynchronize(w.ev[1]));
+                    HX_HIP(hipEventElapsedTime(&ms, w.ev[0], w.ev[1]));
+                }
+                if (ms < best) {
+                    best = ms;
+                    choice = c;
+                }
+            }
+        }
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_store_locked(key, choice);
+    }
+    if ((rc = setup_tiles(choice.block))) return rc;
+    const int block = choice.block;
+    int64_t grid = o.grid_blocks ? std::max<int64_t>(8, (o.grid_blocks + 7) / 8 * 8) : grid_for(choice, n_tiles, cus);
+    grid = std::min<int64_t>(grid, 1ll << 30);
+    if (st) {
+        st->block_threads = block;
+        st->grid_blocks = grid;
+    }
+    const int list_grid = cus * 8;
+    const int drain_grid = cus;
+
+    uint64_t prev_remaining = 0;
+    for (int round = 0;; ++round) {
+        ++w.epoch;
+        q.epoch = w.epoch;
+        launch_reset(w.cnt, s);
+        const TopArgs ta = first_args();
         if (timing && round == 0) HX_HIP(hipEventRecord(w.ev[0], s));
-        if (round == 0) {
+        const bool filter = round == 0 && o.precision == HEXVAL_FP32_FILTER;
+        if (filter) {
+            launch_filter_range(ta, batched, (int)grid, block, s);
+            if (timing) HX_HIP(hipEventRecord(w.ev[3], s));
+            launch_top_list(ta, batched, list_grid, block, s);
+        } else if (round == 0) {
             launch_top_range(ta, batched, (int)grid, block, s);
         } else {
             CollectArgs ca{q, single, dmeshes, batched ? n_meshes : 1};
@@ -452,18 +599,28 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
             launch_top_list(ta, batched, list_grid, block, s);
         }
         if (timing && round == 0) HX_HIP(hipEventRecord(w.ev[1], s));
-        RootArgs ra{q, single, dmeshes};
-        launch_roots(ra, cus * 2, s);
-        DrainArgs da{q, o.max_depth};
-        launch_drain(da, drain_grid, s);
-        FoldArgs fa{q, single, dmeshes};
-        launch_fold(fa, cus * 2, s);
-        if (timing && round == 0) HX_HIP(hipEventRecord(w.ev[2], s));
         HX_HIP(hipGetLastError());
         HX_HIP(hipMemcpyAsync(w.hcnt, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
         HX_HIP(hipStreamSynchronize(s));
+        // Subdivision only when the first pass listed elements for it.
+        if (w.hcnt->n_sub > 0) {
+            RootArgs ra{q, single, dmeshes};
+            launch_roots(ra, cus * 2, s);
+            DrainArgs da{q, o.max_depth};
+            launch_drain(da, drain_grid, s);
+            FoldArgs fa{q, single, dmeshes};
+            launch_fold(fa, cus * 2, s);
+            HX_HIP(hipGetLastError());
+            HX_HIP(hipMemcpyAsync(w.hcnt, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        }
+        if (timing && round == 0) HX_HIP(hipEventRecord(w.ev[2], s));
+        HX_HIP(hipStreamSynchronize(s));
         const Counters c = *w.hcnt;
-        if (c.error) return fail(HEXVAL_E_QUEUE, "subdivision drain stalled (error bits %u)", c.error);
+        if (c.error)
+            return fail(HEXVAL_E_QUEUE,
+                        "subdivision drain stalled (error bits %u; %llu subdivided, %llu nodes evaluated, "
+                        "%llu queued, %llu outstanding)",
+                        c.error, c.n_sub, c.n_nodes, c.node_tail, c.outstanding);
         if (st) {
             st->n_subdivided += (int64_t)std::min<uint64_t>(c.n_sub, q.node_cap);
             st->n_nodes += (int64_t)c.n_nodes;
@@ -471,7 +628,13 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
             st->n_rounds = round + 1;
             if (round == 0) {
                 st->n_elements = total;
-                if (timing) {
+                if (o.precision == HEXVAL_FP32_FILTER) st->n_recheck = (int64_t)std::min<uint64_t>(c.n_list, q.list_cap);
+                if (timing && o.precision == HEXVAL_FP32_FILTER) {
+                    hipEventElapsedTime(&st->ms_first_pass, w.ev[0], w.ev[3]);
+                    hipEventElapsedTime(&st->ms_recheck, w.ev[3], w.ev[1]);
+                    hipEventElapsedTime(&st->ms_subdivision, w.ev[1], w.ev[2]);
+                    hipEventElapsedTime(&st->ms_total, w.ev[0], w.ev[2]);
+                } else if (timing) {
                     hipEventElapsedTime(&st->ms_first_pass, w.ev[0], w.ev[1]);
                     hipEventElapsedTime(&st->ms_subdivision, w.ev[1], w.ev[2]);
                     hipEventElapsedTime(&st->ms_total, w.ev[0], w.ev[2]);

@@ -12,6 +12,7 @@ namespace hexval {
 int fail(int code, const char* fmt, ...);
 const char* last_error();
 int current_device(int* dev, int* cus);
+const char* device_arch(int dev);
 void default_opts(hexval_opts_t* o);
 int check_opts(const hexval_opts_t* o);
 

@@ -172,12 +172,36 @@ void hexval_emul_exact(const double* pts, int64_t n, int max_depth, uint8_t* ver
     for (int64_t e = 0; e < n; ++e) verdicts[e] = exact_verdict(pts + 24 * e, max_depth);
 }
 
-// Bound constants of the kernels: {tau_value, tau_coeff, tau_level, u}.
+// First-pass quantities of the lean kernels (precision 0: FP64, 1: FP32
+// filter): m20 (min of the values tested at step 2), mb (min b_9..b_27),
+// min27, scale M^, certified-range flag, and the state the kernel takes
+// (FP64: 0..4 as hexval_emul_values; FP32: 0 INVALID, 1 VALID, -1 recheck).
+void hexval_emul_lean(const double* pts, const int32_t* conn, int64_t n, int precision, int check_edges,
+                      double* m20, double* mb, double* min27, double* scale, int32_t* state)
+{
+    for (int64_t e = 0; e < n; ++e) {
+        V3 p[8];
+        double raw[24];
+        gather(pts, conn, e, p, raw);
+        if (precision == 0) {
+            const LeanResult r = element_lean(p, check_edges != 0);
+            m20[e] = r.m20; mb[e] = r.mb; min27[e] = r.min27; scale[e] = r.scale;
+            state[e] = lean_state(r, check_edges ? 0 : 6);
+        } else {
+            const LeanT<float> r = element_lean_t<float>(p, check_edges != 0);
+            m20[e] = r.m20; mb[e] = r.mb; min27[e] = r.min27; scale[e] = r.scale;
+            state[e] = filter_state(r);
+        }
+    }
+}
+
+// Bound constants of the kernels: {tau_value, tau_coeff, tau_level, u64, u32}.
 void hexval_emul_constants(double* out)
 {
     out[0] = kTauValue;
     out[1] = kTauCoeff;
     out[2] = kTauLevel;
     out[3] = kU64;
+    out[4] = kU32;
 }
 }

@@ -35,7 +35,9 @@ class hexval_stats_t(ctypes.Structure):
                 ("n_recheck", ctypes.c_int64), ("n_rounds", ctypes.c_int64),
                 ("max_level", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("ms_first_pass", ctypes.c_float), ("ms_recheck", ctypes.c_float),
-                ("ms_subdivision", ctypes.c_float), ("ms_total", ctypes.c_float)]
+                ("ms_subdivision", ctypes.c_float), ("ms_total", ctypes.c_float),
+                ("block_threads", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -148,3 +148,68 @@ def batched_meshes(n_meshes=10000, lo=2.0, hi=6.0, seed=4):
     for m, ((nx, ny, nz), a) in enumerate(zip(dims, amps)):
         V, conn = warped_lattice(nx, ny, nz, jitter=a, jitter_all=True, seed=[seed, m])
         yield V, conn
+
+
+# ---------------------------------------------------------------- on device
+
+def warped_lattice_torch(nx, ny, nz, amp=0.2, wavelength=16.0, jitter=0.0, seed=0, device="cuda"):
+    """warped_lattice generated on the device with torch (every vertex jittered
+    by U(-jitter, jitter)^3 from a Philox stream seeded with `seed`).  Returns
+    (vertices float64 [M,3], connectivity int32 [N,8]) device tensors."""
+    import torch
+    w = 2.0 * math.pi / wavelength
+    i = torch.arange(nx + 1, dtype=torch.float64, device=device)
+    j = torch.arange(ny + 1, dtype=torch.float64, device=device)
+    k = torch.arange(nz + 1, dtype=torch.float64, device=device)
+    si, sj, sk = torch.sin(w * i), torch.sin(w * j), torch.sin(w * k)
+    V = torch.empty((nz + 1, ny + 1, nx + 1, 3), dtype=torch.float64, device=device)
+    V[..., 0] = i[None, None, :] + amp * (sj[None, :, None] * sk[:, None, None])
+    V[..., 1] = j[None, :, None] + amp * (sk[:, None, None] * si[None, None, :])
+    V[..., 2] = k[:, None, None] + amp * (si[None, None, :] * sj[None, :, None])
+    V = V.reshape(-1, 3)
+    if jitter > 0:
+        g = torch.Generator(device=device)
+        g.manual_seed(int(seed))
+        V += (torch.rand(V.shape, dtype=torch.float64, device=device, generator=g) * 2.0 - 1.0) * jitter
+    sx, sy = nx + 1, (nx + 1) * (ny + 1)
+    base = (torch.arange(nx, dtype=torch.int32, device=device)[None, None, :]
+            + sx * torch.arange(ny, dtype=torch.int32, device=device)[None, :, None]
+            + sy * torch.arange(nz, dtype=torch.int32, device=device)[:, None, None]).reshape(-1, 1)
+    off = torch.tensor([0, 1, 1 + sx, sx, sy, 1 + sy, 1 + sx + sy, sx + sy], dtype=torch.int32,
+                       device=device)
+    return V, (base + off[None, :]).contiguous()
+
+
+def batched_meshes_torch(n_meshes=10000, lo=2.0, hi=6.0, seed=4, device="cuda"):
+    """The batched workload on the device: mesh m is a warped lattice with
+    every vertex jittered by U(-a_m, a_m)^3, a_m ~ U(0, 0.6), hex counts
+    log-uniform in [10^lo, 10^hi] (dimensions from batched_mesh_sizes).
+    Yields (V, conn) device tensors; jitter stream of mesh m seeded seed*1e6+m."""
+    dims, amps = batched_mesh_sizes(n_meshes, lo, hi, seed)
+    for m, ((nx, ny, nz), a) in enumerate(zip(dims, amps)):
+        yield warped_lattice_torch(nx, ny, nz, jitter=float(a), seed=seed * 1_000_000 + m,
+                                   device=device)
+
+
+def near_degenerate_mesh_torch(n_lattice_cells, seed=0, device="cuda"):
+    """A serving request mesh generated as in the precision-stress workload:
+    a warped lattice of about n cells (1% of vertices jittered 0.8) plus 5%
+    near-degenerate independent hexes; lattice on the device, the appended
+    hexes from near_degenerate_hexes (host) copied over."""
+    import torch
+    n = max(1, int(n_lattice_cells))
+    nx = max(1, int(round(n ** (1.0 / 3.0))))
+    nz = max(1, int(round(n / (nx * nx))))
+    V, C = warped_lattice_torch(nx, nx, nz, seed=seed, device=device)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) + 7)
+    sel = torch.rand(V.shape[0], dtype=torch.float64, device=device, generator=g) < 0.01
+    V[sel] += (torch.rand((int(sel.sum()), 3), dtype=torch.float64, device=device, generator=g) * 2 - 1) * 0.8
+    n_extra = int(round(0.05 * C.shape[0]))
+    if n_extra:
+        P = torch.from_numpy(near_degenerate_hexes(n_extra, seed=int(seed) + 11)).to(device)
+        extra = (V.shape[0] + torch.arange(8 * n_extra, dtype=torch.int64, device=device)).to(
+            torch.int32).reshape(n_extra, 8)
+        V = torch.cat([V, P.reshape(-1, 3)])
+        C = torch.cat([C, extra])
+    return V.contiguous(), C.contiguous()

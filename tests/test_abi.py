@@ -27,10 +27,10 @@ def test_library_exports_every_declared_function():
 
 
 def test_struct_layouts_match_header_sizes():
-    # int64 alignment: mesh 32 B, opts 48 B, stats 72 B, request 64 B
+    # int64 alignment: mesh 32 B, opts 48 B, stats 88 B, request 64 B
     assert ctypes.sizeof(hx.hexval_mesh_t) == 32
     assert ctypes.sizeof(hx.hexval_opts_t) == 48
-    assert ctypes.sizeof(hx.hexval_stats_t) == 72
+    assert ctypes.sizeof(hx.hexval_stats_t) == 88
     assert ctypes.sizeof(hx.hexval_request_t) == 64
 
 

@@ -1,0 +1,96 @@
+"""GPU: the batched entry point (one persistent launch over many meshes)
+gives, for every mesh, the results of checking that mesh alone, and they
+agree with the oracle; the autotuned launch shape never changes results."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1706_01613_amd import hexval as hx
+from paper_1706_01613_amd import synth
+from tests._gpu import assert_parity, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _alone(torch, V, C, **kw):
+    v, m, _ = hx.check(V, C, **kw)
+    torch.cuda.synchronize()
+    return v, m
+
+
+def _batched(torch, meshes, precision=hx.FP64, stats=None, **kw):
+    vs = [torch.empty(C.shape[0] if C is not None else V.shape[0], dtype=torch.uint8, device="cuda")
+          for V, C in meshes]
+    ms = [torch.empty(v.shape[0], dtype=torch.float64, device="cuda") for v in vs]
+    descs = [hx.make_mesh(V, C) for V, C in meshes]
+    opts = hx.make_opts(precision=precision, stream=torch.cuda.current_stream(), stats=stats, **kw)
+    hx.hexval_check_batched(descs, opts, vs, ms)
+    torch.cuda.synchronize()
+    return vs, ms
+
+
+@pytest.mark.parametrize("precision", [hx.FP64, hx.FP32_FILTER])
+def test_batched_equals_alone_and_oracle(precision):
+    torch = torch_cuda()
+    _say(f"batched 60 meshes precision {precision}")
+    meshes = list(synth.batched_meshes_torch(60, lo=1.0, hi=4.5, seed=11))
+    # mixed layouts: a few [n,8,3] meshes and an empty one
+    for s in range(3):
+        P = torch.from_numpy(synth.independent_hexes(500 + 137 * s, noise=0.45, seed=50 + s)).cuda()
+        meshes.append((P, None))
+    meshes.append((torch.empty((0, 3), dtype=torch.float64, device="cuda"),
+                   torch.empty((0, 8), dtype=torch.int32, device="cuda")))
+    st = hx.hexval_stats_t()
+    vs, ms = _batched(torch, meshes, precision, stats=st)
+    assert st.n_elements == sum(v.shape[0] for v in vs)
+    for k, ((V, C), v, m) in enumerate(zip(meshes, vs, ms)):
+        va, ma = _alone(torch, V, C, precision=precision)
+        assert torch.equal(v, va), k
+        assert torch.equal(torch.nan_to_num(m, 7.0), torch.nan_to_num(ma, 7.0)), k
+    for k in list(range(0, 64, 7)):
+        V, C = meshes[k]
+        Vh = V.cpu().numpy()
+        Ch = C.cpu().numpy() if C is not None else None
+        assert_parity(vs[k].cpu().numpy(), ms[k].cpu().numpy() if precision == hx.FP64 else None,
+                      Vh, Ch, label=f"mesh {k}")
+
+
+def test_launch_shape_does_not_change_results():
+    torch = torch_cuda()
+    V, C = synth.warped_lattice_torch(60, 50, 40, jitter=0.4, seed=3)
+    ref = _alone(torch, V, C)
+    for block, grid in [(64, 0), (128, 16), (256, 0), (256, 1024), (192, 4096)]:
+        v, m = _alone(torch, V, C, block_threads=block, grid_blocks=grid)
+        assert torch.equal(v, ref[0]) and torch.equal(m, ref[1]), (block, grid)
+    vs, ms = _batched(torch, [(V, C), (V, C)], block_threads=64, grid_blocks=64)
+    assert torch.equal(vs[0], ref[0]) and torch.equal(vs[1], ref[0])
+
+
+def test_config4_full_size_batched():
+    """10,000 meshes, hex counts log-uniform in [1e2, 1e6] (about 1.1e9 hexes),
+    every vertex jittered by U(0, 0.6) cell, FP32 filter + FP64, cap 6, one
+    persistent launch; a sample of meshes is checked against the oracle."""
+    torch = torch_cuda()
+    _say("config 4: generating 10,000 meshes on the device")
+    meshes = list(synth.batched_meshes_torch(10000, seed=4))
+    total = sum(C.shape[0] for _, C in meshes)
+    _say(f"config 4: {total} hexes")
+    st = hx.hexval_stats_t()
+    st.timing = 1
+    vs, ms = _batched(torch, meshes, hx.FP32_FILTER, stats=st)
+    _say(f"config 4 stats: {st.as_dict()}")
+    assert st.n_elements == total and total > 5e8
+    rng = np.random.default_rng(0)
+    sizes = np.array([C.shape[0] for _, C in meshes])
+    sample = list(rng.choice(len(meshes), 12, replace=False)) + [int(sizes.argmax())]
+    for k in sample:
+        V, C = meshes[k]
+        _say(f"config 4: oracle on mesh {k} ({C.shape[0]} hexes)")
+        assert_parity(vs[k].cpu().numpy(), None, V.cpu().numpy(), C.cpu().numpy(), label=f"mesh {k}")

@@ -161,3 +161,49 @@ def test_repeated_runs_are_bitwise_identical():
     runs = [_run(torch, P)[:2] for _ in range(3)]
     for v, m in runs[1:]:
         assert (v == runs[0][0]).all() and np.array_equal(m, runs[0][1])
+
+
+# ------------------------------------------------------------ FP32 filter
+
+U32 = 2.0 ** -24
+
+
+def _fp32_min_bound(points, conn=None):
+    """Bound of the FP32-decided min_coeff: 256 u32 M (M from the oracle's
+    scale, within a factor of the kernel's)."""
+    return 300.0 * U32 * oracle.scale(points, conn)
+
+
+@pytest.mark.parametrize("case", ["config1", "lattice", "stress", "tangled"])
+def test_fp32_filter_verdicts_identical(case):
+    torch = torch_cuda()
+    _say(f"fp32 filter {case}")
+    conn = None
+    if case == "config1":
+        P = synth.independent_hexes(300000, seed=0)
+    elif case == "lattice":
+        P, conn = synth.warped_lattice(48, 40, 32, seed=2)
+    elif case == "stress":
+        V, C = synth.warped_lattice(40, 40, 40, seed=3)
+        P, conn = synth.append_independent(V, C, synth.near_degenerate_hexes(6400, seed=1))
+    else:
+        P = synth.independent_hexes(100000, noise=0.6, seed=4)
+    v, m, st = _run(torch, P, conn, precision=hx.FP32_FILTER)
+    v64, m64, _ = _run(torch, P, conn)
+    assert (v == v64).all()
+    ref = assert_parity(v, None, P, conn, label=f"fp32 {case}")
+    bound = _fp32_min_bound(P, conn)
+    ok = np.isfinite(ref["min_coeff"])
+    assert (np.abs(m[ok] - ref["min_coeff"][ok]) <= bound[ok]).all()
+    assert st["n_recheck"] > 0 or case == "lattice"
+    if case == "stress":
+        # every near-degenerate element goes to the FP64 recheck
+        assert st["n_recheck"] >= 6400
+
+
+def test_fp32_filter_small_list_defers_to_fp64_rounds():
+    torch = torch_cuda()
+    P = synth.near_degenerate_hexes(20000, seed=7)
+    # FP32 filter with a 64-node subdivision queue: deferred FP64 passes
+    v, m, st = _run(torch, P, precision=hx.FP32_FILTER, queue_capacity=64)
+    assert_parity(v, None, P, label="fp32 rounds")

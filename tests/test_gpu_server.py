@@ -1,0 +1,115 @@
+"""GPU: the request queue with continuous batching.  Each request's result is
+the same alone and in the mix (bitwise: the arithmetic of an element never
+depends on what else runs), host-uploaded requests match device-resident
+ones, and admission respects the HBM budget."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1706_01613_amd import hexval as hx
+from paper_1706_01613_amd import loadgen, synth
+from tests._gpu import assert_parity, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _pool(torch, n, seed, lo=3.0, hi=5.3):
+    rng = np.random.default_rng(seed)
+    sizes = np.rint(10.0 ** rng.uniform(lo, hi, size=n)).astype(int)
+    return [synth.near_degenerate_mesh_torch(int(s), seed=seed * 100 + k) for k, s in enumerate(sizes)]
+
+
+def _alone(torch, V, C, precision):
+    v, m, _ = hx.check(V, C, precision=precision)
+    torch.cuda.synchronize()
+    return v, m
+
+
+def _templates(meshes, host=False):
+    out = []
+    for V, C in meshes:
+        r = hx.hexval_request_t()
+        r.mesh = hx.make_mesh(V, C)
+        if host:
+            r.mesh.points = None
+            r.mesh.connectivity = None
+            r.host_points = V.data_ptr()
+            r.host_conn = C.data_ptr()
+        out.append(r)
+    return out
+
+
+def _outputs(torch, arena, off, n):
+    v = arena[off:off + n]
+    a = off + (n + 7) // 8 * 8
+    m = arena[a:a + 8 * n].view(torch.float64)
+    return v, m
+
+
+@pytest.mark.parametrize("precision", [hx.FP64, hx.FP32_FILTER])
+def test_server_mix_equals_alone(precision):
+    torch = torch_cuda()
+    meshes = _pool(torch, 10, seed=3)
+    alone = [_alone(torch, V, C, precision) for V, C in meshes]
+    opts = hx.make_opts(precision=precision)
+    sv = hx.hexval_server_create(opts, 8 << 30, 4)
+    try:
+        # 40 requests, all arriving at once (maximal overlap), then 40 spread out
+        idx = np.arange(40) % 10
+        arrival = np.concatenate([np.zeros(20), np.linspace(0, 0.02, 20)])
+        sizes = [meshes[i][1].shape[0] for i in idx]
+        arena = torch.empty(loadgen.arena_bytes(sizes), dtype=torch.uint8, device="cuda")
+        lat, st, off, wall = loadgen.run(sv, arrival, idx, _templates(meshes), arena)
+        torch.cuda.synchronize()
+        assert (st == hx.OK).all()
+        for k, i in enumerate(idx):
+            v, m = _outputs(torch, arena, int(off[k]), sizes[k])
+            assert torch.equal(v, alone[i][0]), k
+            assert torch.equal(torch.nan_to_num(m, 7.0), torch.nan_to_num(alone[i][1], 7.0)), k
+        assert (lat > 0).all()
+    finally:
+        hx.hexval_server_destroy(sv)
+    V, C = meshes[0]
+    assert_parity(alone[0][0].cpu().numpy(), None, V.cpu().numpy(), C.cpu().numpy(), label="pool 0")
+
+
+def test_server_host_upload_and_budget():
+    torch = torch_cuda()
+    meshes = _pool(torch, 6, seed=5, lo=4.0, hi=5.0)
+    host = [(V.cpu().pin_memory(), C.cpu().pin_memory()) for V, C in meshes]
+    alone = [_alone(torch, V, C, hx.FP64) for V, C in meshes]
+    # budget: the slot workspaces plus room for about one uploaded mesh
+    up = max(V.numel() * 8 + C.numel() * 4 for V, C in meshes)
+    opts = hx.make_opts()
+    per_slot = 2 * (1 << 20) * 272 + 2 ** 16 * 220 + (1 << 20) * 12   # generous estimate
+    sv = hx.hexval_server_create(opts, 2 * per_slot + int(1.2 * up) + (64 << 20), 2)
+    try:
+        idx = np.arange(12) % 6
+        sizes = [meshes[i][1].shape[0] for i in idx]
+        arena = torch.empty(loadgen.arena_bytes(sizes), dtype=torch.uint8, device="cuda")
+        tmpl = _templates(host, host=True)
+        for t, (V, C) in zip(tmpl, host):
+            t.mesh.n_points = V.shape[0]
+        lat, st, off, _ = loadgen.run(sv, np.zeros(12), idx, tmpl, arena)
+        torch.cuda.synchronize()
+        assert (st == hx.OK).all()
+        for k, i in enumerate(idx):
+            v, m = _outputs(torch, arena, int(off[k]), sizes[k])
+            assert torch.equal(v, alone[i][0]), k
+        # a request whose upload can never fit is refused at submission
+        big = hx.hexval_request_t()
+        big.mesh = hx.hexval_mesh_t(None, 1 << 33, None, 1 << 33)
+        big.host_points = host[0][0].data_ptr()
+        big.host_conn = host[0][1].data_ptr()
+        big.verdicts = arena.data_ptr()
+        with pytest.raises(hx.HexvalError) as e:
+            hx.hexval_server_submit(sv, big)
+        assert e.value.status == hx.E_BUSY
+    finally:
+        hx.hexval_server_destroy(sv)

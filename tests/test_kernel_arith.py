@@ -23,6 +23,7 @@ def emul():
     E.hexval_emul_values.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, P, P, P, P]
     E.hexval_emul_exact.argtypes = [P, ctypes.c_int64, ctypes.c_int, P]
     E.hexval_emul_constants.argtypes = [P]
+    E.hexval_emul_lean.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int, P, P, P, P, P]
     return E
 
 
@@ -112,9 +113,9 @@ def test_kernel_error_bounds_hold(emul, kind):
         X = X * 10.0 ** rng.uniform(-3, 3, size=(n, 1, 1))
     if kind == "stress":
         X = synth.near_degenerate_hexes(n, seed=5)
-    k = np.empty(4)
+    k = np.empty(5)
     emul.hexval_emul_constants(k.ctypes.data)
-    tau_v, tau_b, _, u = k
+    tau_v, tau_b, _, u, _ = k
     c, s = values(emul, X)
     worst = 0.0
     for P, cc, m in zip(X, c, s):
@@ -124,3 +125,56 @@ def test_kernel_error_bounds_hold(emul, kind):
             t = (tau_v if a < 8 else tau_b) * u * m
             worst = max(worst, float(e) / t)
     assert worst < 1.0
+
+
+def lean(E, pts, precision, check_edges=0):
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 8, 3)
+    n = pts.shape[0]
+    out = [np.empty(n) for _ in range(4)]
+    st = np.empty(n, np.int32)
+    E.hexval_emul_lean(pts.ctypes.data, None, n, precision, check_edges,
+                       *[o.ctypes.data for o in out], st.ctypes.data)
+    return out + [st]
+
+
+@pytest.mark.parametrize("kind", ["random", "offset", "scaled", "stress", "tangled"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lean_minima_within_certified_bounds(emul, kind, precision):
+    """The first-pass minima (FP64 pass and FP32 filter) stay within the
+    thresholds the kernels certify with: |m8^ - m8| < tau_value u M^ and
+    |mb^ - mb| < tau_coeff u M^, against exact values."""
+    rng = np.random.default_rng(40 + len(kind) + precision)
+    n = 40
+    X = CUBE[None] + rng.uniform(-0.4, 0.4, size=(n, 8, 3))
+    if kind == "offset":
+        X = X + rng.uniform(100, 1000, size=(n, 1, 3))
+    if kind == "scaled":
+        X = X * 10.0 ** rng.uniform(-3, 3, size=(n, 1, 1))
+    if kind == "stress":
+        X = synth.near_degenerate_hexes(n, seed=6)
+    if kind == "tangled":
+        X = CUBE[None] + rng.uniform(-0.7, 0.7, size=(n, 8, 3))
+    k = np.empty(5)
+    emul.hexval_emul_constants(k.ctypes.data)
+    u = k[3] if precision == 0 else k[4]
+    m20, mb, _, scale, _ = lean(emul, X, precision)
+    worst = 0.0
+    for P, a, b, s in zip(X, m20, mb, scale):
+        be, _ = exact.coefficients(P)
+        m8e, mbe = min(be[:8]), min(be[8:])
+        worst = max(worst, float(abs(Fraction(float(a)) - m8e)) / (k[0] * u * s),
+                    float(abs(Fraction(float(b)) - mbe)) / (k[1] * u * s))
+    assert worst < 1.0
+
+
+def test_fp32_filter_decisions_agree_with_oracle(emul):
+    X = np.concatenate([synth.independent_hexes(100000, seed=0),
+                        synth.near_degenerate_hexes(20000, seed=1),
+                        synth.independent_hexes(20000, noise=0.6, seed=2)])
+    _, _, _, _, st = lean(emul, X, 1)
+    ref = oracle.check(X)["verdict"]
+    decided = st >= 0
+    assert (st[decided] == ref[decided]).all()
+    assert decided.mean() > 0.8
+    # the near-degenerate corners are never certified in FP32
+    assert not decided[100000:120000].any()
