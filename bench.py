@@ -170,6 +170,46 @@ def serving_leg(hx, torch, synth, capacity_hex_s, n_req=2000, n_pool=32, seed=5)
     return out
 
 
+def batched_leg(hx, torch, synth, steps):
+    """Batched workload: 10,000 meshes, hex counts log-uniform in [1e2, 1e6],
+    every vertex jittered by U(-a_m, a_m)^3 with a_m ~ U(0, 0.6), FP32 filter +
+    FP64, depth cap 6: one persistent launch per step, against one
+    hexval_check_ex call per mesh."""
+    meshes = list(synth.batched_meshes_torch(10000, seed=4))
+    total = int(sum(C.shape[0] for _, C in meshes))
+    vs = [torch.empty(C.shape[0], dtype=torch.uint8, device="cuda") for _, C in meshes]
+    ms = [torch.empty(C.shape[0], dtype=torch.float64, device="cuda") for _, C in meshes]
+    descs = [hx.make_mesh(V, C) for V, C in meshes]
+    stream = torch.cuda.current_stream()
+    res = {"workload": "10,000 warped lattices, 1e2..1e6 hexes (log-uniform), all vertices jittered "
+                       "U(0,0.6) cell, FP32 filter + FP64, cap 6", "hexes": total, "meshes": len(meshes)}
+    for name, prec in (("fp32_filter", hx.FP32_FILTER), ("fp64", hx.FP64)):
+        st = hx.hexval_stats_t()
+        st.timing = 1
+        opts = hx.make_opts(precision=prec, stream=stream, stats=st)
+        hx.hexval_check_batched(descs, opts, vs, ms)      # warm-up + tuning
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            hx.hexval_check_batched(descs, opts, vs, ms)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        res[name] = {"value": total / wall, "unit": "hex/s", "ms_per_step": 1e3 * wall,
+                     "stats": st.as_dict()}
+    # the same meshes one call at a time (FP32 filter)
+    opts = hx.make_opts(precision=hx.FP32_FILTER, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d, v, m in zip(descs, vs, ms):
+        hx.hexval_check_ex(d, opts, v, m)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    res["fp32_filter_one_call_per_mesh"] = {"value": total / wall, "unit": "hex/s", "ms_per_pass": 1e3 * wall}
+    res["speedup_batched_vs_per_mesh"] = res["fp32_filter"]["value"] / res["fp32_filter_one_call_per_mesh"]["value"]
+    del meshes, vs, ms, descs
+    return res
+
+
 def copy_calibration(torch, nbytes=1 << 30):
     """A plain device copy of known size, for scaling the profiler's
     FETCH_SIZE / WRITE_SIZE counters."""
@@ -261,6 +301,10 @@ def main():
         torch.cuda.empty_cache()
         out["fp32_filter_vs_fp64"] = fp32_leg(hx, torch, synth, max(5, args.steps // 2), stream)
         log(f"fp32 leg {out['fp32_filter_vs_fp64']}")
+        torch.cuda.empty_cache()
+        log("batched leg")
+        out["batched"] = batched_leg(hx, torch, synth, 3)
+        log(f"batched leg {out['batched']}")
         torch.cuda.empty_cache()
         log("serving leg")
         out["serving"] = serving_leg(hx, torch, synth, value)

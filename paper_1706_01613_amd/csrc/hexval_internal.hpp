@@ -17,8 +17,8 @@ constexpr uint32_t kFlagUndecided = 2u;  // a sub-box at the cap certainly ambig
 constexpr uint32_t kFlagExact = 4u;      // a decision could not be certified
 constexpr uint32_t kFlagOverflow = 8u;   // a child did not fit in the queue
 
-// Error bits reported by kernels.
-constexpr uint32_t kErrSpinTimeout = 1u;
+// Largest depth cap accepted (levels 0..kMaxDepth).
+constexpr int kMaxDepth = 20;
 
 // One element of one mesh, as the kernels see it.
 struct MeshDev {
@@ -33,32 +33,30 @@ struct MeshDev {
     int32_t pad;
 };
 
-// A sub-box waiting in the subdivision queue: 27 coefficients in tensor
-// order, possibly mirrored (see `orient`), the element's bound scale, the
-// index of the element in the subdivided list and the level.  256 bytes.
+// A stored sub-box of the subdivision: 27 coefficients in tensor order,
+// possibly mirrored (see `orient`), the element's bound scale, the index of
+// the element in the subdivided list and the level.  256 bytes, so that eight
+// lanes load one node as a single 256-byte span.
 struct alignas(256) Node {
     double b[27];
     double scale;
     int64_t slot;      // index into the subdivided-element arrays
     int32_t level;
     int32_t orient;    // bit d set: axis d stored mirrored
-    uint64_t pad;
-    uint64_t ready;    // written last (release): the epoch of the pass that wrote the node
+    uint64_t pad[2];
 };
 
-struct Counters {
-    unsigned long long node_tail;     // node slots reserved
-    unsigned long long node_head;     // node slots claimed by the drain
-    unsigned long long outstanding;   // nodes queued or in process
+// Counters of one pass.
+struct alignas(256) Counters {
+    // lvl[l]: sub-boxes of level l reserved (l = 0: the roots).  Stored
+    // sub-boxes of level l occupy nodes[base_l, base_l + min(lvl[l], cap -
+    // base_l)) with base_0 = 0 and base_{l+1} = base_l + that count.
+    unsigned long long lvl[kMaxDepth + 4];
     unsigned long long n_sub;         // subdivided elements (slots used)
     unsigned long long n_exact;       // elements listed for the exact tier
     unsigned long long n_deferred;    // elements deferred to a later pass
-    unsigned long long n_nodes;       // sub-boxes evaluated
-    unsigned long long n_recheck;     // FP32 filter: elements listed for FP64
     unsigned long long n_list;        // entries in the FP64 (re)check list
-    unsigned int max_level;
-    unsigned int error;
-    unsigned long long pad[5];
+    unsigned long long pad[4];
 };
 
 struct QueueDev {
@@ -74,7 +72,6 @@ struct QueueDev {
     int32_t* list_mesh;
     uint64_t list_cap;
     Counters* cnt;
-    uint64_t epoch;        // pass number; a node is ready when node.ready == epoch
 };
 
 }  // namespace hexval

@@ -5,9 +5,11 @@
 //                  decisions of Section 6 steps 2 and 4; ambiguous elements
 //                  are compacted (ballot + one atomic per wave) into the
 //                  subdivision queue, uncertain ones into the exact list.
-//   k_drain        persistent drain of the subdivision queue: eight lanes per
-//                  node, one lane per child (de Casteljau at 1/2), children
-//                  that stay ambiguous are pushed back until the depth cap.
+//   k_roots        root sub-boxes (level 0) of the subdivided elements.
+//   k_level        one level of the subdivision: eight lanes per stored
+//                  sub-box, one lane per child (de Casteljau at 1/2);
+//                  children that stay ambiguous are appended as the next
+//                  level until the depth cap.
 //   k_fold         folds the per-element flags of subdivided elements into
 //                  verdicts (INVALID > exact > overflow > UNDECIDED > VALID).
 //   small kernels  counter reset, batched tile table, deferred-element
@@ -52,16 +54,6 @@ __device__ __forceinline__ void wave_count(unsigned long long* c, bool pred)
     const uint64_t mask = ballot(pred);
     if (mask && (threadIdx.x & 63) == __ffsll((unsigned long long)mask) - 1)
         atomicAdd(c, (unsigned long long)__popcll(mask));
-}
-
-__device__ __forceinline__ uint64_t load_acquire(const uint64_t* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void store_release(uint64_t* p, uint64_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint64_t load_relaxed64(const uint64_t* p)
@@ -199,10 +191,7 @@ __global__ __launch_bounds__(256) void k_roots(RootArgs a)
     const QueueDev& q = a.q;
     const unsigned long long ns = q.cnt->n_sub;
     const int64_t n = (int64_t)(ns < q.node_cap ? ns : q.node_cap);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        q.cnt->node_tail = (unsigned long long)n;
-        q.cnt->outstanding = (unsigned long long)n;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) q.cnt->lvl[0] = (unsigned long long)n;
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
          s += (int64_t)gridDim.x * blockDim.x) {
         const int mi = q.sub_mesh[s];
@@ -215,7 +204,6 @@ __global__ __launch_bounds__(256) void k_roots(RootArgs a)
         Node* nd = q.nodes + s;
         write_root(nd, r, s);
         q.sub_flags[s] = 0u;
-        store_release(&nd->ready, q.epoch);
     }
 }
 
@@ -352,162 +340,131 @@ __device__ __forceinline__ int mirrored(int t, int pattern)
     return mi + 3 * mj + 9 * mk;
 }
 
-// Claims up to 32 queued slots for the calling wave: returns the first slot
-// and sets *count (0 when nothing is queued right now).  Only slots below
-// node_tail (reserved by a producer, so written soon) are ever claimed.
-__device__ __forceinline__ unsigned long long claim_slots(Counters* cnt, uint64_t cap, int* count)
-{
-    const int lane = threadIdx.x & 63;
-    unsigned long long h = 0, n = 0;
-    if (lane == 0) {
-        for (int tries = 0; tries < 4; ++tries) {
-            h = load_relaxed(&cnt->node_head);
-            unsigned long long t = load_relaxed(&cnt->node_tail);
-            if (t > cap) t = cap;
-            if (h >= t) {
-                n = 0;
-                break;
-            }
-            n = t - h < 32 ? t - h : 32;
-            if (atomicCAS(&cnt->node_head, h, h + n) == h) break;
-            n = 0;
-        }
-    }
-    *count = (int)wave_bcast(n, 0);
-    return wave_bcast(h, 0);
-}
-
-// Watchdog of the drain: a wave that waits gives up (error flag) only when
-// the whole queue has made no progress (processed-node counter unchanged) for
-// 4 s of the 100 MHz real-time clock, so every wave is bound to exit.
-struct Watchdog {
-    unsigned long long seen = ~0ull;
-    uint64_t since = 0;
-    __device__ bool expired(Counters* cnt)
-    {
-        const int lane = threadIdx.x & 63;
-        unsigned long long now_nodes = 0;
-        if (lane == 0) now_nodes = load_relaxed(&cnt->n_nodes);
-        now_nodes = wave_bcast(now_nodes, 0);
-        const uint64_t t = __builtin_amdgcn_s_memrealtime();
-        if (now_nodes != seen) {
-            seen = now_nodes;
-            since = t;
-            return false;
-        }
-        return t - since > 400000000ull;
-    }
+// Range of the stored sub-boxes of level L (see Counters::lvl).  Every
+// count it reads is final: it was produced by an earlier launch.
+struct LevelRange {
+    uint64_t base, count, next_base;
 };
 
-__global__ __launch_bounds__(256) void k_drain(DrainArgs a)
+__device__ LevelRange level_range(const Counters* cnt, int L, uint64_t cap)
 {
+    uint64_t base = 0, count = 0;
+    for (int l = 0; l <= L; ++l) {
+        base += count;
+        const uint64_t c = cnt->lvl[l];
+        count = c < cap - base ? c : cap - base;
+    }
+    return {base, count, base + count};
+}
+
+// Orders this wave's LDS writes before its later LDS reads by other lanes
+// (a compiler barrier: one wave's LDS accesses complete in issue order).
+__device__ __forceinline__ void lds_order() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
+constexpr int kNodeWords = 30;   // words of a Node that carry data
+
+// One level of the adaptive subdivision (Section 6, step 5).  Each stored
+// sub-box of level L gets eight lanes of a wave, one per child octant: the
+// group copies the node into LDS (one 256-byte span), every lane takes its
+// octant's coefficients by de Casteljau at 1/2 (on the mirrored tensor
+// order) and applies the certified decisions.  Children that stay ambiguous
+// below the depth cap are appended as level L+1: a block reserves room for
+// the children of its 32 sub-boxes with one atomic.  Waves of a block move in
+// step over consecutive groups of 32 sub-boxes.
+__global__ __launch_bounds__(256) void k_level(LevelArgs a)
+{
+    __shared__ double stage_mem[4][8][kNodeWords];
+    __shared__ unsigned int wave_push[4];
+    __shared__ unsigned long long block_base;
+    const int wid = threadIdx.x >> 6;
+    double (*stage)[kNodeWords] = stage_mem[wid];
     const int lane = threadIdx.x & 63;
     const int grp = lane >> 3;
     const int child = lane & 7;
     const QueueDev& q = a.q;
     Counters* cnt = q.cnt;
     const uint64_t cap = q.node_cap;
-    Watchdog dog;
-    for (;;) {
-        int n = 0;
-        const unsigned long long h = claim_slots(cnt, cap, &n);
-        if (n == 0) {
-            unsigned long long out = 0;
-            if (lane == 0) out = load_relaxed(&cnt->outstanding);
-            out = wave_bcast(out, 0);
-            if (out == 0) return;
-            __builtin_amdgcn_s_sleep(1);
-            if (dog.expired(cnt)) {
-                if (lane == 0) atomicOr(&cnt->error, kErrSpinTimeout);
-                return;
+    const LevelRange r = level_range(cnt, a.level, cap);
+    const int level = a.level + 1;   // level of the children evaluated here
+    const double* nodes = reinterpret_cast<const double*>(q.nodes);
+    for (uint64_t b0 = (uint64_t)blockIdx.x * 32; b0 < r.count; b0 += (uint64_t)gridDim.x * 32) {
+        const uint64_t i = b0 + (uint64_t)(wid * 8 + grp);
+        const bool act = i < r.count;
+        if (act) {
+            // 8 lanes x 32 bytes: the whole node (words 30, 31 are padding)
+            const double2* src = reinterpret_cast<const double2*>(nodes + (r.base + i) * 32 + 4 * child);
+            const double2 w0 = src[0], w1 = src[1];
+            double* dst = stage[grp] + 4 * child;
+            dst[0] = w0.x;
+            dst[1] = w0.y;
+            if (child < 7) {
+                dst[2] = w1.x;
+                dst[3] = w1.y;
             }
-            continue;
         }
-        for (int sub = 0; sub < n; sub += 8) {
-        const uint64_t slot = h + sub + grp;
-        bool pending = sub + grp < n;
-        while (ballot(pending)) {
-            // Poll with relaxed loads (no cache maintenance per poll); one
-            // acquire fence once a node is seen complete.
-            const bool ready = pending && load_relaxed64(&q.nodes[slot].ready) == q.epoch;
-            const uint64_t rmask = ballot(ready);
-            if (!rmask) {
-                __builtin_amdgcn_s_sleep(1);
-                if (dog.expired(cnt)) {
-                    if (lane == 0) atomicOr(&cnt->error, kErrSpinTimeout);
-                    return;
-                }
-                continue;
+        lds_order();
+        bool push = false, invalid = false, undecided = false, inexact = false;
+        double t[27];
+        int64_t sslot = 0;
+        double scale = 0.0;
+        if (act) {
+            const double* nd = stage[grp];
+            const uint64_t lo = __double_as_longlong(nd[29]);
+            const int pat = (int)(lo >> 32) ^ child;
+            sslot = (int64_t)__double_as_longlong(nd[28]);
+            scale = nd[27];
+#pragma unroll
+            for (int k = 0; k < 27; ++k) t[k] = nd[mirrored(k, pat)];
+            const bool dead = (__hip_atomic_load(q.sub_flags + sslot, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT) & kFlagInvalid) != 0u;
+            if (!dead) {
+                lower_octant(t);
+                const double tau = level_threshold(scale, level);
+                const double m8 = fmin(fmin(fmin(t[0], t[2]), fmin(t[6], t[8])),
+                                       fmin(fmin(t[18], t[20]), fmin(t[24], t[26])));
+                double m19 = t[1];
+#pragma unroll
+                for (int k = 3; k < 26; ++k)
+                    if (k != 6 && k != 8 && k != 18 && k != 20 && k != 24) m19 = fmin(m19, t[k]);
+                if (m8 <= -tau) invalid = true;
+                else if (!(m8 > tau)) inexact = true;
+                else if (m19 > tau) { /* positive on this sub-box */ }
+                else if (level < a.max_depth) push = true;
+                else if (m19 <= -tau) undecided = true;
+                else inexact = true;
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            // ---- one child of a ready node per lane
-            bool push = false, invalid = false, undecided = false, inexact = false;
-            double t[27];
-            int level = 0;
-            int64_t sslot = 0;
-            double scale = 0.0;
-            if (ready) {
-                const Node* nd = q.nodes + slot;
-                const int pat = nd->orient ^ child;
-                level = nd->level + 1;
-                sslot = nd->slot;
-                scale = nd->scale;
+        }
+        uint32_t fl = (invalid ? kFlagInvalid : 0u) | (undecided ? kFlagUndecided : 0u) |
+                      (inexact ? kFlagExact : 0u);
+        // room for the children that stay ambiguous: one atomic per block
+        const uint64_t pmask = ballot(push);
+        if (lane == 0) wave_push[wid] = (unsigned int)__popcll(pmask);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned int total = wave_push[0] + wave_push[1] + wave_push[2] + wave_push[3];
+            block_base = total ? atomicAdd(&cnt->lvl[level], (unsigned long long)total) : 0ull;
+        }
+        __syncthreads();
+        if (pmask) {
+            unsigned long long off = block_base + (unsigned long long)lane_rank(pmask);
+            for (int w = 0; w < wid; ++w) off += wave_push[w];
+            const uint64_t ns = r.next_base + off;
+            if (push) {
+                if (ns < cap) {
+                    double* out = reinterpret_cast<double*>(q.nodes + ns);
 #pragma unroll
-                for (int k = 0; k < 27; ++k) t[k] = nd->b[mirrored(k, pat)];
-                const bool dead = (__hip_atomic_load(q.sub_flags + sslot, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT) & kFlagInvalid) != 0u;
-                if (!dead) {
-                    lower_octant(t);
-                    const double tau = level_threshold(scale, level);
-                    const double m8 = fmin(fmin(fmin(t[0], t[2]), fmin(t[6], t[8])),
-                                           fmin(fmin(t[18], t[20]), fmin(t[24], t[26])));
-                    double m19 = t[1];
-#pragma unroll
-                    for (int k = 3; k < 26; ++k)
-                        if (k != 6 && k != 8 && k != 18 && k != 20 && k != 24) m19 = fmin(m19, t[k]);
-                    if (m8 <= -tau) invalid = true;
-                    else if (!(m8 > tau)) inexact = true;
-                    else if (m19 > tau) { /* positive on this sub-box */ }
-                    else if (level < a.max_depth) push = true;
-                    else if (m19 <= -tau) undecided = true;
-                    else inexact = true;
-                }
-            }
-            const uint32_t fl = (invalid ? kFlagInvalid : 0u) | (undecided ? kFlagUndecided : 0u) |
-                                (inexact ? kFlagExact : 0u);
-            const uint64_t pmask = ballot(push);
-            if (pmask) {
-                const unsigned long long ns = wave_reserve(&cnt->node_tail, pmask);
-                const bool stored = push && ns < cap;
-                const uint64_t smask = ballot(stored);
-                if (smask && lane == __ffsll((unsigned long long)pmask) - 1)
-                    atomicAdd(&cnt->outstanding, (unsigned long long)__popcll(smask));
-                if (stored) {
-                    Node* out = q.nodes + ns;
-#pragma unroll
-                    for (int k = 0; k < 27; ++k) out->b[k] = t[k];
-                    out->scale = scale;
-                    out->slot = sslot;
-                    out->level = level;
-                    out->orient = child;
-                    store_release(&out->ready, q.epoch);
-                } else if (push) {
-                    atomicOr(q.sub_flags + sslot, kFlagOverflow);
+                    for (int k = 0; k < 27; ++k) out[k] = t[k];
+                    out[27] = scale;
+                    out[28] = __longlong_as_double(sslot);
+                    out[29] = __longlong_as_double((long long)((uint64_t)(uint32_t)level |
+                                                               ((uint64_t)(uint32_t)child << 32)));
+                } else {
+                    fl |= kFlagOverflow;
                 }
             }
-            if (fl) atomicOr(q.sub_flags + sslot, fl);
-            // one atomic per counter and wave
-            int lv = ready ? level : 0;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) lv = max(lv, __shfl_xor(lv, d, 64));
-            if (lane == 0) {
-                atomicAdd(&cnt->n_nodes, (unsigned long long)__popcll(rmask));
-                atomicSub(&cnt->outstanding, (unsigned long long)(__popcll(rmask) / 8));
-                atomicMax(&cnt->max_level, (unsigned int)lv);
-            }
-            pending = pending && !ready;
         }
-        }
+        if (fl) atomicOr(q.sub_flags + sslot, fl);
+        __syncthreads();   // wave_push and block_base are rewritten next round
     }
 }
 
@@ -687,7 +644,7 @@ void launch_top_list(const TopArgs& a, bool batched, int grid, int block, hipStr
     else HX_LAUNCH((k_top_f64_list<false, false>), grid, block, s, a);
 }
 
-void launch_drain(const DrainArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_drain, grid, 256, s, a); }
+void launch_level(const LevelArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_level, grid, 256, s, a); }
 void launch_roots(const RootArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_roots, grid, 256, s, a); }
 void launch_fold(const FoldArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_fold, grid, 256, s, a); }
 void launch_reset(Counters* c, hipStream_t s) { HX_LAUNCH(k_reset, 1, 64, s, c); }

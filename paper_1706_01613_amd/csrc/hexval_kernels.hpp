@@ -18,8 +18,9 @@ struct TopArgs {
     int32_t xcds;                         // tile chunks (1 or 8)
 };
 
-struct DrainArgs {
+struct LevelArgs {
     QueueDev q;
+    int32_t level;       // level of the stored sub-boxes expanded
     int32_t max_depth;
 };
 
@@ -61,7 +62,7 @@ struct ScatterArgs {
 void launch_top_range(const TopArgs& a, bool batched, int grid, int block, hipStream_t s);
 void launch_filter_range(const TopArgs& a, bool batched, int grid, int block, hipStream_t s);
 void launch_top_list(const TopArgs& a, bool batched, int grid, int block, hipStream_t s);
-void launch_drain(const DrainArgs& a, int grid, hipStream_t s);
+void launch_level(const LevelArgs& a, int grid, hipStream_t s);
 void launch_roots(const RootArgs& a, int grid, hipStream_t s);
 void launch_fold(const FoldArgs& a, int grid, hipStream_t s);
 void launch_reset(Counters* c, hipStream_t s);

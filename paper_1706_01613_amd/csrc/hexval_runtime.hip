@@ -188,12 +188,6 @@ int Workspace::ensure(uint64_t want_nodes, uint64_t want_list, uint64_t want_mes
             release_queue();
             return rc;
         }
-        // nodes[].ready holds the epoch of the pass that wrote the node;
-        // fresh memory may hold anything, so clear it once here.
-        if (hipMemset(nodes, 0, want_nodes * sizeof(Node)) != hipSuccess) {
-            release_queue();
-            return fail(HEXVAL_E_HIP, "hipMemset of the subdivision queue failed");
-        }
         node_cap = want_nodes;
     }
     if (want_list > list_cap) {
@@ -241,7 +235,6 @@ QueueDev Workspace::queue() const
     q.list_mesh = list_mesh;
     q.list_cap = list_cap;
     q.cnt = cnt;
-    q.epoch = epoch;
     return q;
 }
 
@@ -294,7 +287,7 @@ int check_opts(const hexval_opts_t* o)
 {
     if (o->precision != HEXVAL_FP64 && o->precision != HEXVAL_FP32_FILTER)
         return fail(HEXVAL_E_ARG, "precision must be HEXVAL_FP64 or HEXVAL_FP32_FILTER");
-    if (o->max_depth < 0 || o->max_depth > 20) return fail(HEXVAL_E_ARG, "max_depth must be in 0..20");
+    if (o->max_depth < 0 || o->max_depth > kMaxDepth) return fail(HEXVAL_E_ARG, "max_depth must be in 0..20");
     if (o->block_threads != 0 && (o->block_threads < 64 || o->block_threads > 256 || o->block_threads % 64))
         return fail(HEXVAL_E_ARG, "block_threads must be 0 or a multiple of 64 in 64..256");
     if (o->queue_capacity < 0) return fail(HEXVAL_E_ARG, "queue_capacity must be >= 0");
@@ -577,12 +570,10 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         st->grid_blocks = grid;
     }
     const int list_grid = cus * 8;
-    const int drain_grid = cus;
+    const int level_grid = cus * 8;
 
     uint64_t prev_remaining = 0;
     for (int round = 0;; ++round) {
-        ++w.epoch;
-        q.epoch = w.epoch;
         launch_reset(w.cnt, s);
         const TopArgs ta = first_args();
         if (timing && round == 0) HX_HIP(hipEventRecord(w.ev[0], s));
@@ -606,8 +597,10 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         if (w.hcnt->n_sub > 0) {
             RootArgs ra{q, single, dmeshes};
             launch_roots(ra, cus * 2, s);
-            DrainArgs da{q, o.max_depth};
-            launch_drain(da, drain_grid, s);
+            for (int L = 0; L < o.max_depth; ++L) {
+                LevelArgs la{q, L, o.max_depth};
+                launch_level(la, level_grid, s);
+            }
             FoldArgs fa{q, single, dmeshes};
             launch_fold(fa, cus * 2, s);
             HX_HIP(hipGetLastError());
@@ -616,15 +609,16 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         if (timing && round == 0) HX_HIP(hipEventRecord(w.ev[2], s));
         HX_HIP(hipStreamSynchronize(s));
         const Counters c = *w.hcnt;
-        if (c.error)
-            return fail(HEXVAL_E_QUEUE,
-                        "subdivision drain stalled (error bits %u; %llu subdivided, %llu nodes evaluated, "
-                        "%llu queued, %llu outstanding)",
-                        c.error, c.n_sub, c.n_nodes, c.node_tail, c.outstanding);
         if (st) {
             st->n_subdivided += (int64_t)std::min<uint64_t>(c.n_sub, q.node_cap);
-            st->n_nodes += (int64_t)c.n_nodes;
-            st->max_level = std::max<int32_t>(st->max_level, (int32_t)c.max_level);
+            // children evaluated: 8 per stored sub-box of levels 0..max_depth-1
+            uint64_t base = 0;
+            for (int L = 0; L < o.max_depth && c.n_sub > 0; ++L) {
+                const uint64_t cnt_l = std::min<uint64_t>(c.lvl[L], q.node_cap - base);
+                base += cnt_l;
+                st->n_nodes += 8 * (int64_t)cnt_l;
+                if (cnt_l) st->max_level = std::max<int32_t>(st->max_level, L + 1);
+            }
             st->n_rounds = round + 1;
             if (round == 0) {
                 st->n_elements = total;
