@@ -35,6 +35,45 @@ def algorithmic_bytes(n_hex, n_vert, with_min=True):
     return 32 * n_hex + 24 * n_vert + n_hex * (9 if with_min else 1)
 
 
+# FP64 VALU issue rate of MI355X: 256 CUs x 64 lanes x 2.4 GHz (one FP64
+# add, multiply, FMA or min per lane per clock).
+VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# FP64 arithmetic operations per hex of the first pass (add, sub, mul, FMA,
+# min each counted once): 36 edge differences, 36 pair sums, 20 triple
+# products at 9 operations, about 80 for Table 3 and about 40 for the minima
+# and the decisions.
+VALU_OPS_PER_HEX = 36 + 36 + 20 * 9 + 80 + 40
+KERNEL_SOURCES = ["hexval_kernels.hip", "hexval_kernels.hpp", "hexval_math.hpp", "hexval_internal.hpp"]
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_top_f64_range_lattice400_traffic.md")
+
+
+def kernel_source_digest():
+    """sha256 over the sources the first-pass kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1706_01613_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per first-pass launch from the committed counter profile, or
+    None when the kernel sources have changed since it was taken."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        key, _, val = line.strip().partition(": ")
+        if key in ("traffic_bytes_per_launch", "source_sha256"):
+            vals[key] = val.strip()
+    if vals.get("source_sha256") != kernel_source_digest() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
 def run_steps(hx, torch, pts, conn, steps, precision, stream):
     """Runs `steps` calls; returns (wall seconds, per-call stats list)."""
     n = conn.shape[0]
@@ -261,6 +300,7 @@ def main():
     first = np.array([s["ms_first_pass"] for s in stats])
     alg = algorithmic_bytes(n_hex, n_vert)
     achieved = alg / (first.mean() * 1e-3) / 1e9
+    valu_ops = VALU_OPS_PER_HEX * n_hex / (first.mean() * 1e-3)
     v_host = verdicts.cpu().numpy()
     hist = np.bincount(v_host, minlength=4)[:4].tolist()
     log(f"{value:.4g} hex/s, {ms_step:.3f} ms/step, first pass {first.mean():.3f} ms "
@@ -286,10 +326,12 @@ def main():
                    "hexes": n_hex, "vertices": n_vert, "max_depth": 6, "precision": "fp64",
                    "inputs": "resident in HBM"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_top_f64_range (first pass)",
                      "algorithmic_bytes_per_launch": alg,
-                     "avg_launch_ms": float(first.mean())},
+                     "avg_launch_ms": float(first.mean()),
+                     "valu": {"achieved": valu_ops, "peak": VALU_PEAK_OPS, "unit": "FP64 lane-ops/s",
+                              "frac": valu_ops / VALU_PEAK_OPS, "ops_per_hex": VALU_OPS_PER_HEX}},
         "verdicts": {"invalid": hist[0], "valid": hist[1], "undecided": hist[2],
                      "bad_input": hist[3]},
         "call_stats": stats[-1],
