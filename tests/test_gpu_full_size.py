@@ -1,0 +1,61 @@
+"""GPU parity at the benchmark's full sizes, in the launch configuration the
+benchmark times (default options: FP64, depth cap 6, tuned block and grid).
+
+Every element is compared with the oracle (the oracle takes a few seconds
+for 64M hexes on the host's cores): verdicts bit-exact, min_coeff within
+1e-12 of the element's largest coefficient.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1706_01613_amd import hexval as hx
+from paper_1706_01613_amd import synth
+from tests._gpu import assert_parity, torch_cuda, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CHUNK = 1 << 22
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _check_all(v, m, V, C, label):
+    for lo in range(0, C.shape[0], CHUNK):
+        hi = min(lo + CHUNK, C.shape[0])
+        assert_parity(v[lo:hi], None if m is None else m[lo:hi], V, C[lo:hi], label=f"{label}[{lo}:{hi}]")
+
+
+def test_config2_400_cubed_lattice_every_element():
+    torch = torch_cuda()
+    _say("config 2: 400^3 warped lattice, 1% of vertices jittered 0.8 (seed 0)")
+    V, C = synth.warped_lattice(400, 400, 400, seed=0)
+    assert C.shape[0] == 64_000_000 and V.shape[0] == 64_481_201
+    v, m, st = hx.check(to_dev(torch, V), to_dev(torch, C), stats=True)
+    torch.cuda.synchronize()
+    v, m = v.cpu().numpy(), m.cpu().numpy()
+    _say(f"config 2 stats: {st}")
+    assert st["n_subdivided"] > 0 and st["n_rounds"] == 1
+    _check_all(v, m, V, C, "config 2")
+    hist = np.bincount(v, minlength=4)
+    assert hist[0] > 0 and hist[1] > 0
+
+
+def test_config3_precision_stress_every_element():
+    torch = torch_cuda()
+    _say("config 3: config 2 + 3.2M near-degenerate independent hexes (seed 1)")
+    V, C = synth.precision_stress()
+    assert C.shape[0] == 67_200_000
+    Vd, Cd = to_dev(torch, V), to_dev(torch, C)
+    v64, m64, st64 = hx.check(Vd, Cd, stats=True)
+    v32, m32, st32 = hx.check(Vd, Cd, precision=hx.FP32_FILTER, stats=True)
+    torch.cuda.synchronize()
+    v64, m64, v32 = v64.cpu().numpy(), m64.cpu().numpy(), v32.cpu().numpy()
+    _say(f"config 3 stats: fp64 {st64} fp32 {st32}")
+    assert (v32 == v64).all()
+    assert st32["n_recheck"] >= 3_200_000
+    _check_all(v64, m64, V, C, "config 3")
