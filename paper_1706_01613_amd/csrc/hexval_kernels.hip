@@ -124,16 +124,13 @@ __device__ void write_root(Node* nd, const ElementValues& r, int64_t slot)
 // wave must call this).  Subdivided elements only get their id listed here;
 // k_roots recomputes their 27 coefficients, which keeps this kernel's
 // register footprint small.
-template <bool EDGES, int G>
-__device__ void process_element(const MeshDev& m, int mesh_idx, int64_t e, bool active,
-                                const QueueDev& q, int max_depth)
+template <bool EDGES>
+__device__ void finish_element(const MeshDev& m, int mesh_idx, int64_t e, bool active, const V3 p[8],
+                               bool bad, const QueueDev& q, int max_depth)
 {
-    V3 p[8];
-    bool bad = false;
     int st = -1;
     double mn = 0.0;
     if (active) {
-        load_points_t<G>(m, e, p, bad);
         if (!bad) {
             const LeanResult r = element_lean(p, EDGES);
             st = lean_state(r, max_depth);
@@ -181,6 +178,16 @@ __device__ void process_element(const MeshDev& m, int mesh_idx, int64_t e, bool 
         m.verdict[e] = v;
         if (m.min_coeff) m.min_coeff[e] = bad ? __builtin_nan("") : mn;
     }
+}
+
+template <bool EDGES, int G>
+__device__ void process_element(const MeshDev& m, int mesh_idx, int64_t e, bool active,
+                                const QueueDev& q, int max_depth)
+{
+    V3 p[8];
+    bool bad = false;
+    if (active) load_points_t<G>(m, e, p, bad);
+    finish_element<EDGES>(m, mesh_idx, e, active, p, bad, q, max_depth);
 }
 
 // Root nodes of the subdivided elements listed by the first pass: the full
@@ -243,6 +250,62 @@ __global__ __launch_bounds__(256) void k_top_f64_range(TopArgs a)
             e = it.t * (int64_t)blockDim.x + threadIdx.x;
         }
         process_element<EDGES, G>(m, mi, e, e < m.n, a.q, a.max_depth);
+    }
+}
+
+// LDS address space pointer, as the direct global-to-LDS loads take it.
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+// Waits until this wave's LDS reads have returned (s_waitcnt lgkmcnt(0)).
+__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+// Waits until every earlier vector memory operation of the wave has completed
+// (s_waitcnt vmcnt(0)).
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Single mesh with trusted connectivity: as k_top_f64_range, but the connectivity of
+// a lane's next element is loaded together with the current element's
+// vertices, so each iteration waits for one round of memory latency, not two
+// dependent ones.  The prefetch goes straight to LDS (global_load_lds_dwordx4:
+// lane i of a wave lands at the wave's base + 16 i) and costs no registers.
+template <bool EDGES>
+__global__ __launch_bounds__(256) void k_top_f64_conn(TopArgs a)
+{
+    __shared__ int4 stage[2][256];   // corners 0-3 and 4-7 of each lane's next element
+    const MeshDev& m = a.mesh;
+    const int wave_base = threadIdx.x & ~63;
+    TileIter it(a.n_tiles, a.xcds);
+    auto prefetch = [&](int64_t t) {
+        int64_t e = t * (int64_t)blockDim.x + threadIdx.x;
+        e = e < m.n ? e : m.n - 1;     // past the end: a valid row, ignored
+        const int* src = m.conn + 8 * e;
+        __builtin_amdgcn_global_load_lds(src, (lds_ptr)&stage[0][wave_base], 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(src + 4, (lds_ptr)&stage[1][wave_base], 16, 0, 0);
+    };
+    if (it.t < it.end) prefetch(it.t);
+    wait_vmem();
+    for (; it.t < it.end; it.t += it.step) {
+        const int64_t e = it.t * (int64_t)blockDim.x + threadIdx.x;
+        const bool active = e < m.n;
+        // this iteration's rows are in LDS: the wait after the previous
+        // iteration's loads covered the prefetch issued before them
+        const int4 c0 = stage[0][threadIdx.x], c1 = stage[1][threadIdx.x];
+        const int idx[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+        // the next rows go out before this element's vertex loads, so both
+        // are in flight together (the last iteration reloads its own rows)
+        const int64_t tn = it.t + it.step;
+        wait_lds();                    // the slots are free: every lane has read its row
+        prefetch(tn < it.end ? tn : it.t);
+        // trusted indices: every lane holds a valid row (lanes past the end
+        // hold row n-1), so the loads need no branch
+        V3 p[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double* v = m.points + 3 * (int64_t)idx[k];
+            p[k] = {v[0], v[1], v[2]};
+        }
+        wait_vmem();                   // vertices and the next rows have landed
+        finish_element<EDGES>(m, 0, e, active, p, false, a.q, a.max_depth);
     }
 }
 
@@ -614,11 +677,11 @@ void launch_top_range(const TopArgs& a, bool batched, int grid, int block, hipSt
 #define HX_TOP(E, G) HX_LAUNCH((k_top_f64_range<false, E, G>), grid, block, s, a)
     if (edges) {
         if (g == kGatherPoints) HX_TOP(true, kGatherPoints);
-        else if (g == kGatherConn) HX_TOP(true, kGatherConn);
+        else if (g == kGatherConn) HX_LAUNCH((k_top_f64_conn<true>), grid, block, s, a);
         else HX_TOP(true, kGatherChecked);
     } else {
         if (g == kGatherPoints) HX_TOP(false, kGatherPoints);
-        else if (g == kGatherConn) HX_TOP(false, kGatherConn);
+        else if (g == kGatherConn) HX_LAUNCH((k_top_f64_conn<false>), grid, block, s, a);
         else HX_TOP(false, kGatherChecked);
     }
 #undef HX_TOP
