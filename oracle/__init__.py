@@ -50,6 +50,9 @@ def _load():
         lib.oracle_T.argtypes = [P]
         lib.oracle_bound_constants.restype = None
         lib.oracle_bound_constants.argtypes = [P]
+        lib.oracle_min_jacobian.restype = None
+        lib.oracle_min_jacobian.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
+                                            ctypes.c_int, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -120,6 +123,27 @@ def coefficients(points, conn=None, threads=0, samples=False):
     c = np.empty((n, 27), np.float64) if samples else None
     lib.oracle_coefficients(_ptr(points), _ptr(conn), n, int(threads), _ptr(b), _ptr(c))
     return (b, c) if samples else b
+
+
+MJ_CONVERGED, MJ_CAPPED, MJ_BAD_INPUT, MJ_OUT_OF_RANGE = 0, 1, 3, 4
+
+
+def min_jacobian(points, conn=None, rtol=1e-3, max_depth=6, threads=0):
+    """Certified bounds lo <= min J <= hi over [0,1]^3 (Section 3.1 bounds
+    sharpened level by level to width rtol * M^/6).  Returns a dict with
+    ``lo``, ``hi`` (float64 [n]), ``status`` (uint8 [n]: 0 converged, 1 depth
+    cap, 3 non-finite input, 4 out of the guard range), ``level`` and
+    ``boxes``."""
+    lib = _load()
+    points, conn, n = _prep(points, conn)
+    lo = np.empty(n, np.float64)
+    hi = np.empty(n, np.float64)
+    status = np.empty(n, np.uint8)
+    level = np.empty(n, np.int32)
+    boxes = np.empty(n, np.int64)
+    lib.oracle_min_jacobian(_ptr(points), _ptr(conn), n, float(rtol), int(max_depth), int(threads),
+                            _ptr(lo), _ptr(hi), _ptr(status), _ptr(level), _ptr(boxes))
+    return dict(lo=lo, hi=hi, status=status, level=level, boxes=boxes)
 
 
 def scale(points, conn=None):

@@ -45,6 +45,7 @@
  */
 #include <stdint.h>
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
 #include <omp.h>
@@ -379,4 +380,133 @@ void oracle_bound_constants(double* out)
     out[0] = 24.0;
     out[1] = 1300.0;
     out[2] = U64;
+}
+
+/* ---- minimum of J to a tolerance -------------------------------------------
+ *
+ * The bounds of Section 3.1: on any box, the smallest of its 27 Bezier
+ * coefficients is a lower bound of J on the box (convex hull property), and
+ * each of its 8 corner coefficients is a value of J, so the smallest corner
+ * value met anywhere is an upper bound of min J.  Subdividing sharpens both
+ * (the method recalled in the introduction, which computes min J to any
+ * prescribed tolerance).  Boxes are processed level by level:
+ *
+ *   U_L  = the smallest corner value over every box of levels 0..L;
+ *   a box B of level L is retired when min_27(B) >= U_L - tol, or when L is the
+ *        depth cap (then the element is reported as capped); retired boxes
+ *        cover the domain, so LB = min over them of min_27(B) <= min J;
+ *   every other box is split into its 8 children (level L + 1).
+ *
+ * The decisions at level L use U_L only (not the corners of level L + 1), so
+ * the result does not depend on the order boxes are visited.  Without the
+ * cap, every retired box has min_27 >= U_final - tol, hence U_final - LB <= tol.
+ * tol = rtol * M^ / 6 (M^ / 6 = S_xi S_eta S_zeta, the element's J scale).
+ *
+ * Outputs are widened by the error bounds (coefficients tau_b, corner values
+ * tau_c: the corner rows of T are unit rows, so a corner coefficient is the
+ * sample itself) and rounded outwards: lo <= min J <= hi.
+ * status: 0 converged, 1 depth cap reached, 3 non-finite input, 4 a scale
+ * outside the guard range (no bounds). */
+enum { MJ_CONVERGED = 0, MJ_CAPPED = 1, MJ_BAD_INPUT = 3, MJ_OUT_OF_RANGE = 4 };
+
+typedef struct {
+    double lo[3], size, min27;
+} MjBox;
+
+static double mj_min27(const double b[27])
+{
+    double m = b[0];
+    for (int a = 1; a < 27; ++a) m = fmin(m, b[a]);
+    return m;
+}
+
+static double mj_min_corner(const double b[27])
+{
+    double m = b[0];
+    for (int a = 1; a < 8; ++a) m = fmin(m, b[a]);
+    return m;
+}
+
+static int min_jacobian_one(const double p[8][3], double rtol, int max_depth, double* lo_out,
+                            double* hi_out, int* level_out, int64_t* boxes_out)
+{
+    *lo_out = *hi_out = NAN;
+    *level_out = 0;
+    *boxes_out = 1;
+    if (!all_finite(p)) return MJ_BAD_INPUT;
+    Hex h;
+    hex_setup(p, &h);
+    if (!h.in_range) return MJ_OUT_OF_RANGE;
+    const double tol = rtol * h.M / 6.0;
+    double c[27], b[27];
+    const double root[3] = {0.0, 0.0, 0.0};
+    box_coefficients(&h, root, 1.0, c, b);
+    double U = mj_min_corner(b);
+    double LB = INFINITY;
+    int capped = 0;
+    int64_t n = 1, cap = 16;
+    MjBox* F = (MjBox*)malloc(sizeof(MjBox) * cap);
+    F[0].lo[0] = F[0].lo[1] = F[0].lo[2] = 0.0;
+    F[0].size = 1.0;
+    F[0].min27 = mj_min27(b);
+    for (int L = 0; n > 0; ++L) {
+        double U_next = U;
+        int64_t m = 0, mcap = 16;
+        MjBox* G = (MjBox*)malloc(sizeof(MjBox) * mcap);
+        for (int64_t i = 0; i < n; ++i) {
+            const MjBox* B = &F[i];
+            if (B->min27 >= U - tol || L >= max_depth) {
+                LB = fmin(LB, B->min27);
+                if (!(B->min27 >= U - tol)) capped = 1;
+                continue;
+            }
+            const double hs = 0.5 * B->size;
+            for (int ch = 0; ch < 8; ++ch) {
+                if (m == mcap) {
+                    mcap *= 2;
+                    G = (MjBox*)realloc(G, sizeof(MjBox) * mcap);
+                }
+                MjBox* K = &G[m++];
+                for (int d = 0; d < 3; ++d) K->lo[d] = B->lo[d] + CORNER[ch][d] * hs;
+                K->size = hs;
+                box_coefficients(&h, K->lo, hs, c, b);
+                K->min27 = mj_min27(b);
+                U_next = fmin(U_next, mj_min_corner(b));
+            }
+        }
+        free(F);
+        F = G;
+        n = m;
+        U = U_next;
+        *boxes_out += m;
+        if (m > 0) *level_out = L + 1;
+    }
+    free(F);
+    *lo_out = nextafter(LB - 1300.0 * U64 * h.M, -INFINITY);
+    *hi_out = nextafter(U + 24.0 * U64 * h.M, INFINITY);
+    return capped ? MJ_CAPPED : MJ_CONVERGED;
+}
+
+/* Certified bounds of min J over [0,1]^3 for n hexahedra (layout as in
+ * oracle_check).  rtol > 0; lo, hi: [n]; status: [n]; level, boxes:
+ * optional [n] (deepest level reached, boxes whose coefficients were formed). */
+void oracle_min_jacobian(const double* pts, const int32_t* conn, int64_t n, double rtol, int max_depth,
+                         int nthreads, double* lo, double* hi, uint8_t* status, int32_t* level,
+                         int64_t* boxes)
+{
+    if (!T_ready) build_T();
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t e = 0; e < n; ++e) {
+        double p[8][3];
+        int lv;
+        int64_t nb;
+        gather(pts, conn, e, p);
+        const int st = min_jacobian_one(p, rtol, max_depth, lo + e, hi + e, &lv, &nb);
+        status[e] = (uint8_t)st;
+        if (level) level[e] = lv;
+        if (boxes) boxes[e] = nb;
+    }
 }
