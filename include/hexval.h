@@ -161,6 +161,43 @@ int hexval_check_batched(const hexval_mesh_t* meshes, int32_t n_meshes,
  */
 int hexval_coefficients(const hexval_mesh_t* mesh, void* stream, double* coeffs);
 
+/* ---- minimum of the Jacobian determinant to a tolerance --------------------
+ * The bounds of Section 3.1, sharpened by subdivision (the method the
+ * introduction recalls, which computes min J to any prescribed tolerance): on
+ * a box, the smallest of its 27 Bezier coefficients is a lower bound of J
+ * (convex hull property) and each corner coefficient is a value of J.  Boxes
+ * are refined level by level: a box of level L is kept as final when its
+ * lower bound is within tol of the smallest corner value found on levels
+ * 0..L, else split in 8 until the depth cap.  tol = rtol * S_xi S_eta S_zeta,
+ * S_d the largest |component| of the element's edge vectors along direction
+ * d (for an undistorted cube of edge h, tol = rtol h^3 = rtol J).  The result
+ * does not depend on the order in which boxes are processed. */
+
+/* Per-element status of hexval_min_jacobian (uint8). */
+enum {
+    HEXVAL_MINJ_CONVERGED = 0,    /* hi - lo <= tol (+ the error margins) */
+    HEXVAL_MINJ_DEPTH_CAP = 1,    /* opts->max_depth reached first: lo <= min J <= hi still holds */
+    HEXVAL_MINJ_QUEUE_FULL = 2,   /* box storage ran out: lo <= min J <= hi still holds */
+    HEXVAL_MINJ_BAD_INPUT = 3,    /* non-finite coordinate or (validated) index out of range: lo = hi = NaN */
+    HEXVAL_MINJ_OUT_OF_RANGE = 4  /* an S_d outside [2^-300, 2^300]: lo = hi = NaN */
+};
+
+/*
+ * hexval_min_jacobian: certified bounds lo[e] <= min over [0,1]^3 of J <= hi[e]
+ * for every element (FP64; both are widened by a rigorous rounding-error bound
+ * and rounded outwards).
+ * mesh: as for hexval_check_ex.  opts: max_depth (default 6), validate_indices,
+ *   queue_capacity (stored boxes; 0 = max(n, 2^19) rounded up to a power of 2,
+ *   at most 2^26), stream, stats; precision must be HEXVAL_FP64.  NULL = defaults.
+ * rtol: relative tolerance, finite and > 0 (see tol above).
+ * lo, hi: device [n] float64.  status: device [n] uint8 (HEXVAL_MINJ_*) or NULL.
+ * Returns when the outputs are final.  With a full box store the elements
+ * concerned report HEXVAL_MINJ_QUEUE_FULL and which ones they are may vary
+ * from run to run; otherwise the outputs are deterministic.
+ */
+int hexval_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts, double rtol,
+                        double* lo, double* hi, uint8_t* status);
+
 /* ---- request queue with continuous batching --------------------------------
  * A server runs a scheduler thread that admits submitted requests while fewer
  * than max_slots are in flight and their device footprint fits the HBM budget,

@@ -57,6 +57,8 @@ struct alignas(256) Counters {
     unsigned long long n_deferred;    // elements deferred to a later pass
     unsigned long long n_list;        // entries in the FP64 (re)check list
     unsigned long long pad[4];
+    // first-pass tile counters, one per XCD chunk, each on a 256-byte line
+    unsigned long long tile_next[8 * 32];
 };
 
 struct QueueDev {

@@ -214,20 +214,53 @@ __global__ __launch_bounds__(256) void k_roots(RootArgs a)
     }
 }
 
-// Tile order: with `xcds` chunks (8 on MI355X) the tiles are split into
-// contiguous chunks, chunk x processed by the blocks that the dispatcher
-// places on XCD x (block b runs on XCD b % 8), so neighbouring tiles, which
-// share vertices, meet in the same L2.
-struct TileIter {
-    int64_t t, end, step;
-    __device__ TileIter(int64_t n_tiles, int xcds)
+// Tile scheduler of the first passes.  The tiles are cut into `xcds`
+// contiguous chunks; chunk x is served first to the blocks that the
+// dispatcher places on XCD x (block b runs on XCD b % xcds, 8 on MI355X), so
+// neighbouring tiles, which share vertices, meet in the same L2.  A block
+// takes runs of consecutive tiles from its chunk's counter (runs of up to 16
+// tiles, fewer when there are few tiles per block, so one atomic serves many
+// tiles), and once its chunk is used up takes runs from the other chunks, so
+// a chunk that costs more (private vertices, say) does not hold up the launch.
+struct TileSched {
+    int64_t n_tiles;
+    int xcds, home;
+    int64_t run;                // tiles per grab
+    unsigned long long* next;   // Counters::tile_next
+    int64_t cur = 0, end = 0;   // the block's current run (block-uniform)
+    __device__ TileSched(int64_t n, int x, Counters* c)
+        : n_tiles(n), xcds(x), home((int)(blockIdx.x % (unsigned)x)), next(c->tile_next)
     {
-        const int64_t G = gridDim.x;
-        const int64_t x = blockIdx.x % xcds, local = blockIdx.x / xcds, per = G / xcds;
-        const int64_t cs = n_tiles * x / xcds, ce = n_tiles * (x + 1) / xcds;
-        t = cs + local;
-        end = ce;
-        step = per;
+        const int64_t per_block = n / ((int64_t)gridDim.x * 4);
+        run = per_block < 1 ? 1 : per_block > 16 ? 16 : per_block;
+    }
+    __device__ void grab(int64_t& lo, int64_t& hi)   // one thread of the block
+    {
+        for (int k = 0; k < xcds; ++k) {
+            const int c = (home + k) % xcds;
+            const int64_t cs = n_tiles * c / xcds, size = n_tiles * (c + 1) / xcds - cs;
+            unsigned long long* ctr = next + 32 * c;
+            if ((int64_t)load_relaxed(ctr) >= size) continue;   // used up: skip the atomic
+            const int64_t i = (int64_t)atomicAdd(ctr, (unsigned long long)run);
+            if (i < size) {
+                lo = cs + i;
+                hi = cs + (i + run < size ? i + run : size);
+                return;
+            }
+        }
+        lo = hi = 0;
+    }
+    // The block's next tile, or -1 when none is left (every thread calls it).
+    __device__ int64_t next_tile()
+    {
+        if (cur < end) return cur++;
+        __shared__ int64_t range[2];
+        __syncthreads();                 // everyone has read the previous run
+        if (threadIdx.x == 0) grab(range[0], range[1]);
+        __syncthreads();
+        cur = range[0];
+        end = range[1];
+        return cur < end ? cur++ : -1;
     }
 };
 
@@ -236,18 +269,19 @@ struct TileIter {
 template <bool BATCHED, bool EDGES, int G>
 __global__ __launch_bounds__(256) void k_top_f64_range(TopArgs a)
 {
-    for (TileIter it(a.n_tiles, a.xcds); it.t < it.end; it.t += it.step) {
+    TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
+    for (int64_t t = ts.next_tile(); t >= 0; t = ts.next_tile()) {
         MeshDev m;
         int mi;
         int64_t e;
         if (BATCHED) {
-            mi = a.tile_mesh[it.t];
+            mi = a.tile_mesh[t];
             m = a.meshes[mi];
-            e = (it.t - m.tile_begin) * (int64_t)blockDim.x + threadIdx.x;
+            e = (t - m.tile_begin) * (int64_t)blockDim.x + threadIdx.x;
         } else {
             mi = 0;
             m = a.mesh;
-            e = it.t * (int64_t)blockDim.x + threadIdx.x;
+            e = t * (int64_t)blockDim.x + threadIdx.x;
         }
         process_element<EDGES, G>(m, mi, e, e < m.n, a.q, a.max_depth);
     }
@@ -274,7 +308,7 @@ __global__ __launch_bounds__(256) void k_top_f64_conn(TopArgs a)
     __shared__ int4 stage[2][256];   // corners 0-3 and 4-7 of each lane's next element
     const MeshDev& m = a.mesh;
     const int wave_base = threadIdx.x & ~63;
-    TileIter it(a.n_tiles, a.xcds);
+    TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
     auto prefetch = [&](int64_t t) {
         int64_t e = t * (int64_t)blockDim.x + threadIdx.x;
         e = e < m.n ? e : m.n - 1;     // past the end: a valid row, ignored
@@ -282,10 +316,11 @@ __global__ __launch_bounds__(256) void k_top_f64_conn(TopArgs a)
         __builtin_amdgcn_global_load_lds(src, (lds_ptr)&stage[0][wave_base], 16, 0, 0);
         __builtin_amdgcn_global_load_lds(src + 4, (lds_ptr)&stage[1][wave_base], 16, 0, 0);
     };
-    if (it.t < it.end) prefetch(it.t);
+    int64_t t = ts.next_tile();
+    if (t >= 0) prefetch(t);
     wait_vmem();
-    for (; it.t < it.end; it.t += it.step) {
-        const int64_t e = it.t * (int64_t)blockDim.x + threadIdx.x;
+    while (t >= 0) {
+        const int64_t e = t * (int64_t)blockDim.x + threadIdx.x;
         const bool active = e < m.n;
         // this iteration's rows are in LDS: the wait after the previous
         // iteration's loads covered the prefetch issued before them
@@ -293,9 +328,9 @@ __global__ __launch_bounds__(256) void k_top_f64_conn(TopArgs a)
         const int idx[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
         // the next rows go out before this element's vertex loads, so both
         // are in flight together (the last iteration reloads its own rows)
-        const int64_t tn = it.t + it.step;
+        const int64_t tn = ts.next_tile();
         wait_lds();                    // the slots are free: every lane has read its row
-        prefetch(tn < it.end ? tn : it.t);
+        prefetch(tn >= 0 ? tn : t);
         // trusted indices: every lane holds a valid row (lanes past the end
         // hold row n-1), so the loads need no branch
         V3 p[8];
@@ -306,6 +341,7 @@ __global__ __launch_bounds__(256) void k_top_f64_conn(TopArgs a)
         }
         wait_vmem();                   // vertices and the next rows have landed
         finish_element<EDGES>(m, 0, e, active, p, false, a.q, a.max_depth);
+        t = tn;
     }
 }
 
@@ -375,18 +411,19 @@ __device__ void filter_element(const MeshDev& m, int mesh_idx, int64_t e, bool a
 template <bool BATCHED, int G>
 __global__ __launch_bounds__(256) void k_filter_f32_range(TopArgs a)
 {
-    for (TileIter it(a.n_tiles, a.xcds); it.t < it.end; it.t += it.step) {
+    TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
+    for (int64_t t = ts.next_tile(); t >= 0; t = ts.next_tile()) {
         MeshDev m;
         int mi;
         int64_t e;
         if (BATCHED) {
-            mi = a.tile_mesh[it.t];
+            mi = a.tile_mesh[t];
             m = a.meshes[mi];
-            e = (it.t - m.tile_begin) * (int64_t)blockDim.x + threadIdx.x;
+            e = (t - m.tile_begin) * (int64_t)blockDim.x + threadIdx.x;
         } else {
             mi = 0;
             m = a.mesh;
-            e = it.t * (int64_t)blockDim.x + threadIdx.x;
+            e = t * (int64_t)blockDim.x + threadIdx.x;
         }
         filter_element<G>(m, mi, e, e < m.n, a.q);
     }
@@ -576,6 +613,315 @@ __global__ __launch_bounds__(256) void k_fold(FoldArgs a)
     }
 }
 
+// ======================================================= minimum of J
+//
+// Certified bounds lo <= min J <= hi over [0,1]^3 (hexval_min_jacobian).  The
+// bounds of Section 3.1: on a box, the smallest of its 27 coefficients bounds
+// J from below (convex hull property) and each corner coefficient is a value
+// of J, so the smallest corner value met bounds min J from above.  They are
+// sharpened level by level: a box of level L is retired when its lower bound
+// is within tol = rtol * M^/6 of U_L, the smallest corner value over the boxes
+// of levels 0..L, or when L is the depth cap; otherwise its 8 children are
+// stored as level L+1.  Decisions at level L read U_L only, so the result does
+// not depend on the order in which boxes are processed.
+//
+// Per subdivided element (slot) three arrays u[0..2] rotate by level: the
+// launch for level L reads U_L from u[L%3], lowers u[(L+1)%3] to
+// min(U_L, corner values of level L+1) for every box it splits, and resets
+// u[(L+2)%3], which the next launch writes.
+
+// Range of the stored boxes of level L.  Children are reserved 8 at a time
+// from a multiple of 8 past the level's base and a box is stored only when
+// all 8 fit, so at levels >= 1 the stored span is the reserved count cut to
+// whole groups of 8 below the capacity (slots past it were never written).
+__device__ LevelRange minj_level_range(const Counters* cnt, int L, uint64_t cap)
+{
+    uint64_t base = 0, count = 0;
+    for (int l = 0; l <= L; ++l) {
+        base += count;
+        const uint64_t c = cnt->lvl[l];
+        const uint64_t room = l == 0 ? cap - base : (cap - base) & ~7ull;
+        count = c < room ? c : room;
+    }
+    return {base, count, base + count};
+}
+
+// Order-preserving map of doubles (never NaN here) to unsigned integers.
+__device__ __forceinline__ unsigned long long ord_of(double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ double of_ord(unsigned long long o)
+{
+    return __longlong_as_double((long long)((o >> 63) ? (o & 0x7FFFFFFFFFFFFFFFull) : ~o));
+}
+
+// Widening of a computed bound: the coefficient error bound at the depth cap
+// (it covers corner values and coefficients of every level), then one ulp
+// outwards for the rounding of the addition.
+__device__ __forceinline__ double minj_margin(double scale, int max_depth)
+{
+    return (kTauCoeff + kTauLevel * max_depth) * kU64 * scale;
+}
+
+__device__ __forceinline__ void minj_write(const MinjArgs& a, int64_t e, double lo, double hi, double scale,
+                                           int st)
+{
+    if (st <= 2) {
+        const double mg = minj_margin(scale, a.max_depth);
+        lo = nextafter(lo - mg, -HUGE_VAL);
+        hi = nextafter(hi + mg, HUGE_VAL);
+    } else {
+        lo = hi = __builtin_nan("");
+    }
+    a.mj.lo[e] = lo;
+    a.mj.hi[e] = hi;
+    if (a.mj.status) a.mj.status[e] = (uint8_t)st;
+}
+
+// Status codes (match HEXVAL_MINJ_* of the C ABI).
+constexpr int kMjConverged = 0, kMjCapped = 1, kMjQueueFull = 2, kMjBadInput = 3, kMjOutOfRange = 4;
+
+// Level 0, one element per lane: the bounds of the whole element from the
+// first-pass arithmetic; elements whose bounds are not yet within tol are
+// listed for subdivision, up to root_cap of them, the rest deferred to the
+// next round.  Later rounds take their elements from in_list.
+__global__ __launch_bounds__(256) void k_minj_top(MinjArgs a)
+{
+    const MeshDev& m = a.mesh;
+    const QueueDev& q = a.q;
+    const int64_t count = a.in_list ? a.in_count : m.n;
+    TileSched ts(a.n_tiles, a.xcds, q.cnt);
+    for (int64_t t = ts.next_tile(); t >= 0; t = ts.next_tile()) {
+        const int64_t i = t * (int64_t)blockDim.x + threadIdx.x;
+        const bool active = i < count;
+        const int64_t e = !active ? 0 : a.in_list ? a.in_list[i] : i;
+        int st = -1;
+        double lo = 0.0, hi = 0.0, scale = 0.0;
+        if (active) {
+            V3 p[8];
+            bool bad = false;
+            load_points(m, e, p, bad);
+            if (bad) {
+                st = kMjBadInput;
+            } else {
+                const LeanResult r = element_lean(p, false);
+                if (!r.certified_range) {
+                    bool finite = true;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        finite = finite && isfinite(p[k].x) && isfinite(p[k].y) && isfinite(p[k].z);
+                    st = finite ? kMjOutOfRange : kMjBadInput;
+                } else {
+                    lo = r.min27;
+                    hi = r.m20;
+                    scale = r.scale;
+                    const double tol = a.mj.rtol * scale / 6.0;
+                    if (lo >= hi - tol) st = kMjConverged;
+                    else if (a.max_depth == 0) st = kMjCapped;
+                }
+            }
+        }
+        const bool push = active && st < 0;
+        const uint64_t pmask = ballot(push);
+        bool defer = false;
+        if (pmask) {
+            const unsigned long long slot = wave_reserve(&q.cnt->n_sub, pmask);
+            if (push) {
+                if (slot < a.root_cap) {
+                    q.sub_elem[slot] = e;
+                    q.sub_mesh[slot] = 0;
+                } else {
+                    defer = true;
+                }
+            }
+        }
+        const uint64_t dmask = ballot(defer);
+        if (dmask) {
+            const unsigned long long d = wave_reserve(&q.cnt->n_deferred, dmask);
+            if (defer) a.out_list[d] = e;
+        }
+        if (active && st >= 0) minj_write(a, e, lo, hi, scale, st);
+    }
+}
+
+// Root boxes of the listed elements: full coefficients, their minimum (word
+// 30 of the node) and the per-element arrays.
+__global__ __launch_bounds__(256) void k_minj_roots(MinjArgs a)
+{
+    const QueueDev& q = a.q;
+    const unsigned long long ns = q.cnt->n_sub;
+    const int64_t n = (int64_t)(ns < a.root_cap ? ns : a.root_cap);
+    if (blockIdx.x == 0 && threadIdx.x == 0) q.cnt->lvl[0] = (unsigned long long)n;
+    const unsigned long long inf = ord_of(HUGE_VAL);
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        V3 p[8];
+        bool bad = false;
+        load_points(a.mesh, q.sub_elem[s], p, bad);
+        ElementValues r;
+        element_values(p, r);
+        Node* nd = q.nodes + s;
+        write_root(nd, r, s);
+        double m27 = coefficient(r, 0), mc = r.c[0];
+#pragma unroll
+        for (int k = 1; k < 27; ++k) m27 = fmin(m27, coefficient(r, k));
+#pragma unroll
+        for (int k = 1; k < 8; ++k) mc = fmin(mc, r.c[k]);
+        reinterpret_cast<double*>(nd)[30] = m27;
+        q.sub_flags[s] = 0u;
+        a.mj.u[0][s] = ord_of(mc);
+        a.mj.u[1][s] = inf;
+        a.mj.u[2][s] = inf;
+        a.mj.ufinal[s] = ord_of(mc);
+        a.mj.lb[s] = inf;
+    }
+}
+
+// One level: eight lanes per stored box (one per child octant).  The box is
+// retired or split by the rule above; a split box gets 8 consecutive slots of
+// level L+1 (one atomic per block of 32 boxes) and every lane writes its
+// child, with the child's minimum coefficient in word 30.  A box whose
+// children do not fit is retired and its element flagged.
+__global__ __launch_bounds__(256) void k_minj_level(MinjArgs a)
+{
+    __shared__ double stage_mem[4][8][32];
+    __shared__ unsigned int wave_split[4];
+    __shared__ unsigned long long block_base;
+    const int wid = threadIdx.x >> 6;
+    double (*stage)[32] = stage_mem[wid];
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 3;
+    const int child = lane & 7;
+    const QueueDev& q = a.q;
+    Counters* cnt = q.cnt;
+    const uint64_t cap = q.node_cap;
+    const int L = a.level;
+    const uint64_t* R = a.mj.u[L % 3];
+    uint64_t* W = a.mj.u[(L + 1) % 3];
+    uint64_t* Z = a.mj.u[(L + 2) % 3];
+    {
+        const unsigned long long ns = cnt->n_sub;
+        const uint64_t n_slots = ns < a.root_cap ? ns : a.root_cap;
+        const unsigned long long inf = ord_of(HUGE_VAL);
+        for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < n_slots;
+             s += (uint64_t)gridDim.x * blockDim.x)
+            Z[s] = inf;
+    }
+    const LevelRange r = minj_level_range(cnt, L, cap);
+    const double* nodes = reinterpret_cast<const double*>(q.nodes);
+    for (uint64_t b0 = (uint64_t)blockIdx.x * 32; b0 < r.count; b0 += (uint64_t)gridDim.x * 32) {
+        const uint64_t i = b0 + (uint64_t)(wid * 8 + grp);
+        const bool act = i < r.count;
+        if (act) {
+            const double2* src = reinterpret_cast<const double2*>(nodes + (r.base + i) * 32 + 4 * child);
+            const double2 w0 = src[0], w1 = src[1];
+            double* dst = stage[grp] + 4 * child;
+            dst[0] = w0.x;
+            dst[1] = w0.y;
+            dst[2] = w1.x;
+            dst[3] = w1.y;
+        }
+        lds_order();
+        bool split = false, capped = false;
+        double lo = 0.0, scale = 0.0, U = 0.0;
+        int64_t sslot = 0;
+        int orient = 0;
+        if (act) {
+            const double* nd = stage[grp];
+            lo = nd[30];
+            scale = nd[27];
+            sslot = (int64_t)__double_as_longlong(nd[28]);
+            orient = (int)((uint64_t)__double_as_longlong(nd[29]) >> 32);
+            U = of_ord(R[sslot]);
+            const bool close = lo >= U - a.mj.rtol * scale / 6.0;
+            split = L == 0 || (!close && L < a.max_depth);
+            capped = !split && !close;
+        }
+        // 8 slots per split box, reserved for the whole block at once
+        const uint64_t smask = ballot(split && child == 0);
+        if (lane == 0) wave_split[wid] = (unsigned int)__popcll(smask);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned int total = wave_split[0] + wave_split[1] + wave_split[2] + wave_split[3];
+            block_base = total ? atomicAdd(&cnt->lvl[L + 1], 8ull * total) : 0ull;
+        }
+        __syncthreads();
+        bool stored = false;
+        uint64_t first = 0;
+        if (split) {
+            unsigned long long rank = (unsigned long long)__popcll(smask & ((1ull << (grp * 8)) - 1ull));
+            for (int w = 0; w < wid; ++w) rank += wave_split[w];
+            first = r.next_base + block_base + 8ull * rank;
+            stored = first + 8 <= cap;
+        }
+        double cmin = HUGE_VAL;
+        if (stored) {
+            double t[27];
+            const double* nd = stage[grp];
+            const int pat = orient ^ child;
+#pragma unroll
+            for (int k = 0; k < 27; ++k) t[k] = nd[mirrored(k, pat)];
+            lower_octant(t);
+            cmin = fmin(fmin(fmin(t[0], t[2]), fmin(t[6], t[8])), fmin(fmin(t[18], t[20]), fmin(t[24], t[26])));
+            double m27 = t[0];
+#pragma unroll
+            for (int k = 1; k < 27; ++k) m27 = fmin(m27, t[k]);
+            double* out = reinterpret_cast<double*>(q.nodes + first + child);
+#pragma unroll
+            for (int k = 0; k < 27; ++k) out[k] = t[k];
+            out[27] = scale;
+            out[28] = __longlong_as_double(sslot);
+            out[29] = __longlong_as_double((long long)((uint64_t)(uint32_t)(L + 1) |
+                                                       ((uint64_t)(uint32_t)child << 32)));
+            out[30] = m27;
+        }
+#pragma unroll
+        for (int d = 1; d < 8; d <<= 1) cmin = fmin(cmin, __shfl_xor(cmin, d, 64));
+        if (act && child == 0) {
+            if (stored) {
+                atomicMin(&W[sslot], ord_of(fmin(U, cmin)));
+                atomicMin(&a.mj.ufinal[sslot], ord_of(cmin));
+            } else {
+                atomicMin(&a.mj.lb[sslot], ord_of(lo));
+                const uint32_t fl = (capped ? kFlagUndecided : 0u) | (split ? kFlagOverflow : 0u);
+                if (fl) atomicOr(q.sub_flags + sslot, fl);
+            }
+        }
+        __syncthreads();   // wave_split and block_base are rewritten next round
+    }
+}
+
+// Outputs of the subdivided elements; an element that ran out of room is
+// deferred to the next round (redone from scratch), or reports QUEUE_FULL
+// with its bounds so far in the final round.  Whole waves iterate together
+// (wave-level list appends).
+__global__ __launch_bounds__(256) void k_minj_fold(MinjArgs a)
+{
+    const QueueDev& q = a.q;
+    const unsigned long long ns = q.cnt->n_sub;
+    const int64_t n = (int64_t)(ns < a.root_cap ? ns : a.root_cap);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s0 = blockIdx.x * (int64_t)blockDim.x; s0 < n; s0 += stride) {
+        const int64_t s = s0 + threadIdx.x;
+        const bool active = s < n;
+        const uint32_t f = active ? q.sub_flags[s] : 0u;
+        const bool over = active && (f & kFlagOverflow);
+        const bool defer = over && !a.final_round;
+        const uint64_t dmask = ballot(defer);
+        if (dmask) {
+            const unsigned long long d = wave_reserve(&q.cnt->n_deferred, dmask);
+            if (defer) a.out_list[d] = q.sub_elem[s];
+        }
+        if (active && !defer) {
+            const int st = over ? kMjQueueFull : (f & kFlagUndecided) ? kMjCapped : kMjConverged;
+            minj_write(a, q.sub_elem[s], of_ord(a.mj.lb[s]), of_ord(a.mj.ufinal[s]), q.nodes[s].scale, st);
+        }
+    }
+}
+
 // ------------------------------------------------------------ small kernels
 
 __global__ void k_reset(Counters* c)
@@ -729,6 +1075,11 @@ void launch_scatter_exact(const ScatterArgs& a, hipStream_t s)
     const int64_t g = (a.n + 255) / 256;
     HX_LAUNCH(k_scatter_exact, g < 1024 ? g : 1024, 256, s, a);
 }
+void launch_minj_top(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_top, grid, 256, s, a); }
+void launch_minj_roots(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_roots, grid, 256, s, a); }
+void launch_minj_level(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_level, grid, 256, s, a); }
+void launch_minj_fold(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_fold, grid, 256, s, a); }
+
 void launch_coefficients(const MeshDev& m, double* out, hipStream_t s)
 {
     const int64_t g = (m.n + 255) / 256;

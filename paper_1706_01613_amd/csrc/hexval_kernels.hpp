@@ -59,6 +59,38 @@ struct ScatterArgs {
     const uint8_t* verdicts;  // [n]
 };
 
+// Minimum of J to a tolerance: per subdivided element (slot) arrays of
+// doubles kept in an order-preserving unsigned encoding (atomicMin).
+struct MinjDev {
+    uint64_t* u[3];      // [node_cap] smallest corner value up to a level (rotating by level)
+    uint64_t* ufinal;    // [node_cap] smallest corner value met at any level
+    uint64_t* lb;        // [node_cap] smallest lower bound of a retired box
+    double rtol;
+    double* lo;          // [n] outputs
+    double* hi;
+    uint8_t* status;     // [n] or nullptr
+};
+
+struct MinjArgs {
+    QueueDev q;
+    MeshDev mesh;
+    MinjDev mj;
+    int64_t n_tiles;
+    const int64_t* in_list;   // later rounds: the elements to redo (nullptr: all n)
+    int64_t in_count;
+    int64_t* out_list;        // elements deferred to the next round (room for n)
+    uint64_t root_cap;        // elements subdivided in this round at most (the rest are deferred)
+    int32_t final_round;      // 1: an element out of room reports QUEUE_FULL instead of deferral
+    int32_t level;
+    int32_t max_depth;
+    int32_t xcds;
+};
+
+void launch_minj_top(const MinjArgs& a, int grid, hipStream_t s);
+void launch_minj_roots(const MinjArgs& a, int grid, hipStream_t s);
+void launch_minj_level(const MinjArgs& a, int grid, hipStream_t s);
+void launch_minj_fold(const MinjArgs& a, int grid, hipStream_t s);
+
 void launch_top_range(const TopArgs& a, bool batched, int grid, int block, hipStream_t s);
 void launch_filter_range(const TopArgs& a, bool batched, int grid, int block, hipStream_t s);
 void launch_top_list(const TopArgs& a, bool batched, int grid, int block, hipStream_t s);

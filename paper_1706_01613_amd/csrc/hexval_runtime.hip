@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -143,6 +144,8 @@ Workspace::~Workspace()
     hfree(h_exact_v);
     dfree(meshes);
     hfree(h_meshes);
+    dfree(minj);
+    dfree(minj_defer);
     dfree(tile_mesh);
     for (auto& e : ev)
         if (e) hipEventDestroy(e);
@@ -210,6 +213,24 @@ int Workspace::ensure(uint64_t want_nodes, uint64_t want_list, uint64_t want_mes
         tile_cap = 0;
         if ((rc = dalloc(&tile_mesh, want_tiles))) return rc;
         tile_cap = want_tiles;
+    }
+    return HEXVAL_OK;
+}
+
+int Workspace::ensure_minj(uint64_t slots, uint64_t elements)
+{
+    int rc;
+    if (slots > minj_cap) {
+        dfree(minj);
+        minj_cap = 0;
+        if ((rc = dalloc(&minj, 5 * slots))) return rc;
+        minj_cap = slots;
+    }
+    if (elements > defer_cap) {
+        dfree(minj_defer);
+        defer_cap = 0;
+        if ((rc = dalloc(&minj_defer, 2 * elements))) return rc;
+        defer_cap = elements;
     }
     return HEXVAL_OK;
 }
@@ -343,7 +364,7 @@ static void run_exact_host(const double* pts, uint8_t* out, int64_t n, int max_d
 
 struct TuneChoice {
     int block = 256;
-    int per_cu = 0;   // 0: one tile per block; k: persistent grid of k blocks per CU
+    int per_cu = 16;   // persistent grid of per_cu blocks per CU (tiles are handed out at run time)
 };
 
 static std::mutex g_tune_mu;
@@ -355,7 +376,7 @@ static std::string tune_key(const char* arch, int precision, int gather, bool ba
     int bucket = 0;
     while ((1ll << (bucket + 1)) <= total) ++bucket;
     char buf[128];
-    snprintf(buf, sizeof buf, "%s/p%d/g%d/b%d/n%d", arch, precision, gather, batched ? 1 : 0, bucket);
+    snprintf(buf, sizeof buf, "v2/%s/p%d/g%d/b%d/n%d", arch, precision, gather, batched ? 1 : 0, bucket);
     return buf;
 }
 
@@ -391,7 +412,7 @@ static void tune_store_locked(const std::string& key, const TuneChoice& c)
 
 static int64_t grid_for(const TuneChoice& c, int64_t n_tiles, int cus)
 {
-    int64_t g = c.per_cu ? std::min<int64_t>(n_tiles, (int64_t)cus * c.per_cu) : n_tiles;
+    int64_t g = std::min<int64_t>(n_tiles, (int64_t)cus * std::max(c.per_cu, 1));
     return std::min<int64_t>(std::max<int64_t>(8, (g + 7) / 8 * 8), 1ll << 30);
 }
 
@@ -439,7 +460,6 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     // Launch shape of the first pass: explicit options, else the tuning cache,
     // else (autotuning on) measured below on this input, else defaults.
     TuneChoice choice;
-    choice.per_cu = batched ? 8 : 0;
     const int gather = batched ? 0 : !meshes[0].connectivity ? 1 : (o.validate_indices ? 3 : 2);
     std::string key;
     bool need_tune = false;
@@ -533,14 +553,14 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     };
     if (need_tune) {
         static const int kBlocks[3] = {64, 128, 256};
-        static const int kSingle[4] = {0, 4, 8, 16}, kBatched[4] = {4, 8, 16, 32};
+        static const int kPerCu[4] = {4, 8, 16, 32};
         float best = 1e30f;
         for (int blk : kBlocks) {
             if ((rc = setup_tiles(blk))) return rc;
             for (int k = 0; k < 4; ++k) {
                 TuneChoice c;
                 c.block = blk;
-                c.per_cu = batched ? kBatched[k] : kSingle[k];
+                c.per_cu = kPerCu[k];
                 const int64_t g = grid_for(c, n_tiles, cus);
                 float ms = 0.0f;
                 for (int rep = 0; rep < 2; ++rep) {
@@ -667,6 +687,142 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     return HEXVAL_OK;
 }
 
+// Certified bounds of min J: first pass (root bounds), then one launch per
+// level for the elements whose bounds are not yet within the tolerance.
+int run_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts_in, double rtol, double* lo, double* hi,
+                     uint8_t* status)
+{
+    hexval_opts_t o;
+    if (opts_in) o = *opts_in;
+    else default_opts(&o);
+    int rc = check_opts(&o);
+    if (rc) return rc;
+    if (o.precision != HEXVAL_FP64) return fail(HEXVAL_E_ARG, "hexval_min_jacobian computes in FP64 only");
+    if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(HEXVAL_E_ARG, "rtol must be finite and > 0");
+    if (!mesh) return fail(HEXVAL_E_ARG, "mesh is NULL");
+    if (mesh->n > 0 && (!lo || !hi)) return fail(HEXVAL_E_ARG, "lo or hi is NULL");
+    if ((rc = check_mesh(mesh, lo, o.validate_indices, 0))) return rc;
+    hexval_stats_t* st = o.stats;
+    if (st) {
+        const int timing = st->timing;
+        memset(st, 0, sizeof *st);
+        st->timing = timing;
+    }
+    const int64_t n = mesh->n;
+    if (n == 0) return HEXVAL_OK;
+    int dev, cus;
+    if ((rc = current_device(&dev, &cus))) return rc;
+    hipStream_t s = (hipStream_t)o.stream;
+
+    // Every split box stores its 8 children: room for as many boxes as
+    // elements by default (at least 2^19, at most 2^26 = 17 GiB).
+    const uint64_t node_cap = o.queue_capacity
+                                  ? (uint64_t)o.queue_capacity
+                                  : pow2_ceil(std::min<uint64_t>(std::max<uint64_t>((uint64_t)n, 1u << 19), 1ull << 26));
+    WorkspaceGuard wg;
+    if ((rc = acquire_workspace(dev, &wg.w))) return rc;
+    Workspace& w = *wg.w;
+    if ((rc = w.ensure(node_cap, 0, 1, 1))) return rc;
+    QueueDev q = w.queue();
+    q.node_cap = std::min<uint64_t>(q.node_cap, node_cap);
+    if ((rc = w.ensure_minj(q.node_cap, (uint64_t)n))) return rc;
+
+    MinjArgs a{};
+    a.q = q;
+    a.mesh.points = mesh->points;
+    a.mesh.conn = mesh->connectivity;
+    a.mesh.n = n;
+    a.mesh.n_points = mesh->n_points;
+    a.mesh.validate = (o.validate_indices && mesh->connectivity) ? 1 : 0;
+    for (int k = 0; k < 3; ++k) a.mj.u[k] = w.minj + (uint64_t)k * w.minj_cap;
+    a.mj.ufinal = w.minj + 3 * w.minj_cap;
+    a.mj.lb = w.minj + 4 * w.minj_cap;
+    a.mj.rtol = rtol;
+    a.mj.lo = lo;
+    a.mj.hi = hi;
+    a.mj.status = status;
+    a.max_depth = o.max_depth;
+    a.xcds = 8;
+    const bool timing = st && st->timing;
+
+    // Rounds: a round subdivides at most root_cap elements (a quarter of the
+    // store, the rest being room for their boxes); elements past it, or that
+    // run out of room, are redone from scratch in the next round.  When a
+    // round completes nothing, root_cap shrinks; at one element, the next
+    // round is final: that element reports QUEUE_FULL if it still does not
+    // fit, and root_cap starts over.
+    int64_t* lists[2] = {w.minj_defer, w.minj_defer + w.defer_cap};
+    int64_t count = n;
+    bool final_round = false;
+    const uint64_t root_cap0 = std::max<uint64_t>(1, q.node_cap / 4);
+    uint64_t root_cap = root_cap0;
+    uint64_t tot_sub = 0, tot_nodes = 0;
+    int max_level = 0;
+    for (int round = 0;; ++round) {
+        a.in_list = round == 0 ? nullptr : lists[(round + 1) & 1];
+        a.in_count = round == 0 ? 0 : count;
+        a.out_list = lists[round & 1];
+        a.final_round = final_round ? 1 : 0;
+        a.root_cap = root_cap;
+        a.n_tiles = (count + 255) / 256;
+        launch_reset(w.cnt, s);
+        if (timing && round == 0) HX_HIP(hipEventRecord(w.ev[0], s));
+        launch_minj_top(a, cus * 8, s);
+        if (timing && round == 0) HX_HIP(hipEventRecord(w.ev[1], s));
+        HX_HIP(hipGetLastError());
+        HX_HIP(hipMemcpyAsync(w.hcnt, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HX_HIP(hipStreamSynchronize(s));
+        if (w.hcnt->n_sub > 0) {
+            launch_minj_roots(a, cus * 2, s);
+            for (int L = 0; L <= o.max_depth; ++L) {
+                a.level = L;
+                launch_minj_level(a, cus * 8, s);
+            }
+            launch_minj_fold(a, cus * 2, s);
+            HX_HIP(hipGetLastError());
+            HX_HIP(hipMemcpyAsync(w.hcnt, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        }
+        HX_HIP(hipStreamSynchronize(s));
+        const Counters& c = *w.hcnt;
+        tot_sub += std::min<uint64_t>(c.n_sub, root_cap);
+        // boxes stored below the roots, and the deepest level holding any
+        uint64_t base = 0;
+        for (int L = 0; L <= o.max_depth + 1 && L < kMaxDepth + 4 && c.n_sub > 0; ++L) {
+            const uint64_t room = L == 0 ? q.node_cap - base : (q.node_cap - base) & ~7ull;
+            const uint64_t cnt_l = std::min<uint64_t>(c.lvl[L], room);
+            base += cnt_l;
+            if (L > 0) tot_nodes += cnt_l;
+            if (cnt_l) max_level = std::max(max_level, L);
+        }
+        if (st) st->n_rounds = round + 1;
+        if (c.n_deferred == 0) break;
+        if (final_round) {
+            final_round = false;
+            root_cap = root_cap0;
+        } else if (c.n_deferred == (uint64_t)count) {   // nothing completed
+            if (root_cap > 1) root_cap = std::max<uint64_t>(1, root_cap / 8);
+            else final_round = true;
+        }
+        count = (int64_t)c.n_deferred;
+    }
+    if (timing) {
+        HX_HIP(hipEventRecord(w.ev[2], s));
+        HX_HIP(hipEventSynchronize(w.ev[2]));
+    }
+    if (st) {
+        st->n_elements = n;
+        st->n_subdivided = (int64_t)tot_sub;
+        st->n_nodes = (int64_t)tot_nodes;
+        st->max_level = max_level;
+        if (timing) {
+            hipEventElapsedTime(&st->ms_first_pass, w.ev[0], w.ev[1]);
+            hipEventElapsedTime(&st->ms_subdivision, w.ev[1], w.ev[2]);
+            hipEventElapsedTime(&st->ms_total, w.ev[0], w.ev[2]);
+        }
+    }
+    return HEXVAL_OK;
+}
+
 int run_coefficients(const hexval_mesh_t* mesh, void* stream, double* coeffs)
 {
     if (!mesh) return fail(HEXVAL_E_ARG, "mesh is NULL");
@@ -705,6 +861,12 @@ int hexval_check(const double* points, const int32_t* connectivity, int64_t n, u
 {
     hexval_mesh_t m{points, 0, connectivity, n};
     return run_check(&m, 1, false, nullptr, &verdicts, &min_coeffs);
+}
+
+int hexval_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts, double rtol, double* lo, double* hi,
+                        uint8_t* status)
+{
+    return run_min_jacobian(mesh, opts, rtol, lo, hi, status);
 }
 
 int hexval_check_ex(const hexval_mesh_t* mesh, const hexval_opts_t* opts, uint8_t* verdicts, double* min_coeffs)

@@ -39,11 +39,16 @@ struct Workspace {
     MeshDev* meshes = nullptr;
     MeshDev* h_meshes = nullptr;
     int32_t* tile_mesh = nullptr;
+    uint64_t* minj = nullptr;     // min-J arrays: 5 x minj_cap (u[0..2], ufinal, lb)
+    uint64_t minj_cap = 0;
+    int64_t* minj_defer = nullptr;   // min-J deferred-element lists: 2 x defer_cap
+    uint64_t defer_cap = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 
     ~Workspace();
     int init();
     int ensure(uint64_t nodes, uint64_t list, uint64_t meshes, uint64_t tiles);
+    int ensure_minj(uint64_t slots, uint64_t elements);
     void release_queue();
     void release_list();
     QueueDev queue() const;
@@ -61,5 +66,9 @@ int run_check(const hexval_mesh_t* meshes, int n_meshes, bool batched, const hex
 // Same, on a caller-owned workspace (nullptr: one from the pool).
 int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const hexval_opts_t* opts,
                  uint8_t* const* verdicts, double* const* mins, Workspace* ws);
+
+// Certified bounds of min J (hexval_min_jacobian).
+int run_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts, double rtol, double* lo, double* hi,
+                     uint8_t* status);
 
 }  // namespace hexval

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libhexval.so")
 INVALID, VALID, UNDECIDED, BAD_INPUT = 0, 1, 2, 3
 OK, E_ARG, E_HIP, E_NOMEM, E_QUEUE, E_BUSY = 0, 1, 2, 3, 4, 5
 FP64, FP32_FILTER = 0, 1
+MINJ_CONVERGED, MINJ_DEPTH_CAP, MINJ_QUEUE_FULL, MINJ_BAD_INPUT, MINJ_OUT_OF_RANGE = 0, 1, 2, 3, 4
 STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_HIP", 3: "E_NOMEM", 4: "E_QUEUE", 5: "E_BUSY"}
 
 
@@ -76,6 +77,9 @@ def lib():
             "hexval_check_batched": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t), I32,
                                                     ctypes.POINTER(hexval_opts_t), P, P]),
             "hexval_coefficients": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t), P, P]),
+            "hexval_min_jacobian": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t),
+                                                   ctypes.POINTER(hexval_opts_t), ctypes.c_double,
+                                                   P, P, P]),
             "hexval_server_create": (ctypes.c_int, [ctypes.POINTER(hexval_opts_t), I64, I32,
                                                     ctypes.POINTER(P)]),
             "hexval_server_submit": (ctypes.c_int, [P, ctypes.POINTER(hexval_request_t),
@@ -175,6 +179,12 @@ def hexval_coefficients(mesh, stream, coeffs):
     return _check(lib().hexval_coefficients(ctypes.byref(mesh), _stream_handle(stream), _addr(coeffs)))
 
 
+def hexval_min_jacobian(mesh, opts, rtol, lo, hi, status=None):
+    """C: hexval_min_jacobian."""
+    return _check(lib().hexval_min_jacobian(ctypes.byref(mesh), ctypes.byref(opts) if opts else None,
+                                            float(rtol), _addr(lo), _addr(hi), _addr(status)))
+
+
 def hexval_server_create(opts, hbm_budget_bytes, max_slots):
     h = ctypes.c_void_p()
     _check(lib().hexval_server_create(ctypes.byref(opts) if opts else None, int(hbm_budget_bytes),
@@ -241,3 +251,21 @@ def coefficients(points, connectivity=None, stream=None):
         stream = torch.cuda.current_stream(points.device)
     hexval_coefficients(make_mesh(points, connectivity, n), stream, out)
     return out
+
+
+def min_jacobian(points, connectivity=None, rtol=1e-3, max_depth=6, validate_indices=False,
+                 stream=None, stats=False, queue_capacity=0):
+    """Allocate outputs and run hexval_min_jacobian.  Returns (lo, hi, status,
+    stats dict or None) as torch tensors on points' device."""
+    import torch
+    n = connectivity.shape[0] if connectivity is not None else points.shape[0]
+    lo = torch.empty(n, dtype=torch.float64, device=points.device)
+    hi = torch.empty(n, dtype=torch.float64, device=points.device)
+    status = torch.empty(n, dtype=torch.uint8, device=points.device)
+    st = hexval_stats_t()
+    st.timing = 1 if stats else 0
+    if stream is None:
+        stream = torch.cuda.current_stream(points.device)
+    opts = make_opts(FP64, max_depth, validate_indices, 0, queue_capacity, 0, stream, st)
+    hexval_min_jacobian(make_mesh(points, connectivity, n), opts, rtol, lo, hi, status)
+    return lo, hi, status, (st.as_dict() if stats else None)

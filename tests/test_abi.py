@@ -66,6 +66,16 @@ def test_argument_errors_without_gpu():
     assert L.hexval_check_ex(ctypes.byref(mesh), ctypes.byref(o), 32, None) == hx.E_ARG
     assert L.hexval_check_batched(None, -1, None, None, None) == hx.E_ARG
     assert L.hexval_coefficients(None, None, None) == hx.E_ARG
+    mesh = hx.hexval_mesh_t(16, 0, None, 4)
+    assert L.hexval_min_jacobian(None, None, 1e-3, 32, 48, None) == hx.E_ARG
+    for rtol in (0.0, -1.0, float("nan"), float("inf")):
+        assert L.hexval_min_jacobian(ctypes.byref(mesh), None, rtol, 32, 48, None) == hx.E_ARG
+    assert L.hexval_min_jacobian(ctypes.byref(mesh), None, 1e-3, None, 48, None) == hx.E_ARG
+    o = hx.hexval_opts_default()
+    o.precision = hx.FP32_FILTER
+    assert L.hexval_min_jacobian(ctypes.byref(mesh), ctypes.byref(o), 1e-3, 32, 48, None) == hx.E_ARG
+    empty = hx.hexval_mesh_t(None, 0, None, 0)
+    assert L.hexval_min_jacobian(ctypes.byref(empty), None, 1e-3, None, None, None) == hx.OK
     h = ctypes.c_void_p()
     assert L.hexval_server_create(None, 0, 1, ctypes.byref(h)) == hx.E_ARG
     assert L.hexval_server_create(None, 1 << 30, 0, ctypes.byref(h)) == hx.E_ARG
@@ -80,6 +90,8 @@ def test_no_device_reports_hip_error():
     # valid-looking arguments: the library must stop at the device check
     assert L.hexval_check(16, None, 4, 32, None) == hx.E_HIP
     assert "device" in hx.hexval_last_error()
+    mesh = hx.hexval_mesh_t(16, 0, None, 4)
+    assert L.hexval_min_jacobian(ctypes.byref(mesh), None, 1e-3, 32, 48, None) == hx.E_HIP
     h = ctypes.c_void_p()
     assert L.hexval_server_create(None, 1 << 34, 2, ctypes.byref(h)) == hx.E_HIP
 

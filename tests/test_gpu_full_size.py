@@ -59,3 +59,20 @@ def test_config3_precision_stress_every_element():
     assert (v32 == v64).all()
     assert st32["n_recheck"] >= 3_200_000
     _check_all(v64, m64, V, C, "config 3")
+
+
+def test_config2_min_jacobian_every_element():
+    import oracle
+    torch = torch_cuda()
+    _say("config 2: min J bounds, rtol 1e-3, cap 6")
+    V, C = synth.warped_lattice(400, 400, 400, seed=0)
+    lo, hi, st, stats = hx.min_jacobian(to_dev(torch, V), to_dev(torch, C), rtol=1e-3, stats=True)
+    torch.cuda.synchronize()
+    lo, hi, st = lo.cpu().numpy(), hi.cpu().numpy(), st.cpu().numpy()
+    _say(f"config 2 min J stats: {stats}")
+    assert (st == hx.MINJ_CONVERGED).all()
+    for a in range(0, C.shape[0], CHUNK):
+        b = min(a + CHUNK, C.shape[0])
+        ref = oracle.min_jacobian(V, C[a:b], rtol=1e-3, max_depth=6)
+        assert ((lo[a:b] <= ref["hi"]) & (ref["lo"] <= hi[a:b])).all(), f"[{a}:{b}]"
+        assert (ref["status"] == oracle.MJ_CONVERGED).all()

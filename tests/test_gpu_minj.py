@@ -1,0 +1,154 @@
+"""GPU: certified bounds of min J (hexval_min_jacobian) against the oracle.
+
+Both sides enclose the same number (lo <= min J <= hi), computed with
+different arithmetic, so their refinement may stop at different boxes near
+the tolerance: the parity bar is that every GPU interval meets the oracle's
+(both contain min J), that a converged interval is no wider than tol plus
+the error margins, and that statuses agree on every element whose interval
+is well away from the stopping rule's threshold.  Closed forms and a dense
+grid pin the GPU intervals directly.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1706_01613_amd import hexval as hx
+from paper_1706_01613_amd import synth
+from tests import _ref
+from tests._gpu import torch_cuda, to_dev
+from tests.test_oracle_pins import CUBE, _prism, _twisted
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu(torch, P, conn=None, **kw):
+    lo, hi, st, stats = hx.min_jacobian(to_dev(torch, P), None if conn is None else to_dev(torch, conn),
+                                        stats=True, **kw)
+    torch.cuda.synchronize()
+    return lo.cpu().numpy(), hi.cpu().numpy(), st.cpu().numpy(), stats
+
+
+def _margin(M, max_depth):
+    return (256.0 + 72.0 * max_depth) * U * M
+
+
+def _check_against_oracle(lo, hi, st, P, conn, rtol, max_depth, label):
+    ref = oracle.min_jacobian(P, conn, rtol=rtol, max_depth=max_depth)
+    M = oracle.scale(P, conn)
+    bad = np.isin(ref["status"], (oracle.MJ_BAD_INPUT, oracle.MJ_OUT_OF_RANGE))
+    assert (st[bad] == ref["status"][bad]).all(), label
+    assert np.isnan(lo[bad]).all() and np.isnan(hi[bad]).all(), label
+    ok = ~bad
+    assert (lo[ok] <= hi[ok]).all(), label
+    # both intervals contain min J, so they meet
+    meet = (lo[ok] <= ref["hi"][ok]) & (ref["lo"][ok] <= hi[ok])
+    assert meet.all(), f"{label}: {np.count_nonzero(~meet)} disjoint intervals"
+    conv = ok & (st == hx.MINJ_CONVERGED)
+    width = hi - lo
+    limit = rtol * M / 6 + 2 * _margin(M, max_depth) + 4 * np.spacing(np.abs(lo) + np.abs(hi))
+    assert (width[conv] <= limit[conv]).all(), label
+    return ref
+
+
+@pytest.mark.parametrize("rtol", [1e-2, 1e-4])
+def test_minj_closed_forms(rtol):
+    torch = torch_cuda()
+    thetas = [10, 45, 89, 90, 120, 150, 179]
+    eps = [0.25, 2.0 ** -4, 2.0 ** -10, -2.0 ** -6]
+    P = np.stack([_twisted(t)[0] for t in thetas] + [_prism(e)[0] for e in eps])
+    expect = np.array([math.cos(math.radians(t) / 2) ** 2 for t in thetas] + eps)
+    lo, hi, st, _ = _gpu(torch, P, rtol=rtol, max_depth=14)
+    assert (st == hx.MINJ_CONVERGED).all()
+    assert (lo <= expect + 1e-15).all() and (expect - 1e-15 <= hi).all()
+    M = oracle.scale(P)
+    assert (hi - lo <= rtol * M / 6 + 2 * _margin(M, 14) + 1e-15).all()
+
+
+def test_minj_unit_cube_and_parallelepiped():
+    torch = torch_cuda()
+    A = np.array([[2.0, 0.3, -0.1], [0.2, 1.5, 0.4], [-0.3, 0.1, 0.8]])
+    P = np.stack([CUBE, CUBE @ A.T + 5.0])
+    lo, hi, st, stats = _gpu(torch, P)
+    assert (st == hx.MINJ_CONVERGED).all() and stats["n_subdivided"] == 0
+    for k, v in enumerate([1.0, np.linalg.det(A)]):
+        assert lo[k] <= v <= hi[k] and hi[k] - lo[k] < 1e-11
+
+
+def test_minj_brute_force_grid():
+    torch = torch_cuda()
+    rng = np.random.default_rng(77)
+    P = CUBE[None] + rng.uniform(-0.45, 0.45, size=(300, 8, 3))
+    lo, hi, st, _ = _gpu(torch, P, rtol=1e-3, max_depth=6)
+    for e in range(P.shape[0]):
+        S = _ref.jacobian_grid(P[e], 64).min()
+        slack = 1e-12 * max(1.0, abs(S))
+        assert lo[e] <= S + slack and S <= hi[e] + slack, e
+
+
+@pytest.mark.parametrize("rtol,max_depth", [(1e-3, 6), (1e-5, 8), (1e-2, 0)])
+def test_minj_independent_hexes_against_oracle(rtol, max_depth):
+    torch = torch_cuda()
+    P = synth.independent_hexes(200000, noise=0.35, seed=0)
+    _say(f"minj independent rtol {rtol} depth {max_depth}")
+    lo, hi, st, stats = _gpu(torch, P, rtol=rtol, max_depth=max_depth)
+    _say(f"stats {stats}")
+    ref = _check_against_oracle(lo, hi, st, P, None, rtol, max_depth, "independent")
+    same = np.count_nonzero(st == ref["status"])
+    assert same >= 0.999 * P.shape[0]
+    if max_depth == 0:
+        assert stats["n_subdivided"] == 0
+
+
+def test_minj_lattice_connectivity_against_oracle():
+    torch = torch_cuda()
+    V, C = synth.warped_lattice(48, 40, 32, seed=2, jitter_fraction=0.05)
+    lo, hi, st, stats = _gpu(torch, V, C, rtol=1e-3)
+    _say(f"lattice stats {stats}")
+    assert stats["n_subdivided"] > 0 and stats["max_level"] >= 2
+    _check_against_oracle(lo, hi, st, V, C, 1e-3, 6, "lattice")
+
+
+def test_minj_small_store_rounds_give_identical_results():
+    # a store far too small for the whole mesh: elements that run out of room
+    # are redone in later rounds, and the results equal those of a roomy run
+    torch = torch_cuda()
+    P = synth.independent_hexes(20000, noise=0.45, seed=9)
+    ref = _gpu(torch, P, rtol=1e-5, max_depth=8)
+    lo, hi, st, stats = _gpu(torch, P, rtol=1e-5, max_depth=8, queue_capacity=2000)
+    _say(f"small store stats {stats}")
+    assert stats["n_rounds"] > 1
+    assert np.array_equal(lo, ref[0]) and np.array_equal(hi, ref[1]) and np.array_equal(st, ref[2])
+    assert (st == hx.MINJ_CONVERGED).all()
+
+
+def test_minj_store_smaller_than_one_element_reports_queue_full():
+    # the prism near eps = 0 needs far more boxes than 64 at this tolerance:
+    # the final round reports QUEUE_FULL with a valid enclosure
+    torch = torch_cuda()
+    P, t, d = _prism(2.0 ** -10)
+    lo, hi, st, stats = _gpu(torch, P[None], rtol=1e-9, max_depth=12, queue_capacity=64)
+    assert st[0] == hx.MINJ_QUEUE_FULL
+    assert lo[0] <= 2.0 ** -10 <= hi[0]
+
+
+def test_minj_repeatable_and_bad_input():
+    torch = torch_cuda()
+    P = synth.independent_hexes(50000, noise=0.4, seed=3)
+    P[7, 3, 1] = np.nan
+    P[11] = CUBE * 1e-100
+    a = _gpu(torch, P, rtol=1e-4)
+    b = _gpu(torch, P, rtol=1e-4)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y, equal_nan=True)
+    assert a[2][7] == hx.MINJ_BAD_INPUT and a[2][11] == hx.MINJ_OUT_OF_RANGE
+    assert np.isnan(a[0][7]) and np.isnan(a[1][11])
