@@ -50,6 +50,8 @@ def _load():
         lib.oracle_T.argtypes = [P]
         lib.oracle_bound_constants.restype = None
         lib.oracle_bound_constants.argtypes = [P]
+        lib.oracle_corner_test.restype = ctypes.c_int64
+        lib.oracle_corner_test.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, P, P]
         lib.oracle_min_jacobian.restype = None
         lib.oracle_min_jacobian.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
                                             ctypes.c_int, P, P, P, P, P]
@@ -123,6 +125,24 @@ def coefficients(points, conn=None, threads=0, samples=False):
     c = np.empty((n, 27), np.float64) if samples else None
     lib.oracle_coefficients(_ptr(points), _ptr(conn), n, int(threads), _ptr(b), _ptr(c))
     return (b, c) if samples else b
+
+
+def corner_test(points, conn=None, threads=0):
+    """The corner-only test (Test 1 of Section 7: all 8 corner values of J
+    positive, a necessary condition of validity) and the corner quality (min
+    over the corners of the scaled Jacobian).  Returns a dict with ``test1``
+    (uint8 [n]: 1 VALID, 0 INVALID, 3 BAD_INPUT; uncertified corner signs are
+    settled exactly), ``quality`` (float64 [n], NaN for bad or out-of-range
+    input) and ``fragile`` (ids settled exactly)."""
+    lib = _load()
+    points, conn, n = _prep(points, conn)
+    test1 = np.empty(n, np.uint8)
+    quality = np.empty(n, np.float64)
+    lib.oracle_corner_test(_ptr(points), _ptr(conn), n, int(threads), _ptr(test1), _ptr(quality))
+    fragile = np.nonzero(test1 == FRAGILE)[0]
+    for e in fragile:
+        test1[e] = exact.corner_test(element_points(points, conn, e))
+    return dict(test1=test1, quality=quality, fragile=fragile)
 
 
 MJ_CONVERGED, MJ_CAPPED, MJ_BAD_INPUT, MJ_OUT_OF_RANGE = 0, 1, 3, 4

@@ -176,3 +176,16 @@ def validity(points, max_depth=6):
     else:
         res.update(verdict=UNDECIDED if tree.undecided else VALID)
     return res
+
+
+def corner_test(points):
+    """Test 1 of Section 7 in exact arithmetic: VALID when the 8 corner values
+    of J are all > 0, else INVALID (BAD_INPUT for a non-finite coordinate)."""
+    P = to_fractions(points)
+    if P is None:
+        return BAD_INPUT
+    edges = edge_vectors(P)
+    for n in NODE[:8]:
+        if jacobian(edges, Fraction(n[0], 2), Fraction(n[1], 2), Fraction(n[2], 2)) <= 0:
+            return INVALID
+    return VALID

@@ -510,3 +510,69 @@ void oracle_min_jacobian(const double* pts, const int32_t* conn, int64_t n, doub
         if (boxes) boxes[e] = nb;
     }
 }
+
+/* ---- corner-only test and corner quality ------------------------------------
+ *
+ * Test 1 of the comparison in Section 7: the 8 corner tetrahedra must have
+ * positive volume, i.e. the 8 values of J at the corners (the corner
+ * coefficients b_1..b_8) must be positive.  A corner is a point of the
+ * element, so the test is a necessary condition of validity: it may accept
+ * invalid elements ("false valid") but never rejects a valid one.
+ *
+ * Corner quality (the measure quoted for Fig. 7): the minimum over the 8
+ * corners of the scaled Jacobian J_c / (|e_xi| |e_eta| |e_zeta|), e_* the
+ * three edge vectors that leave the corner; a corner with a zero-length edge
+ * counts as 0.
+ *
+ * test1: 1 VALID (all corner values certainly > 0), 0 INVALID (one certainly
+ * <= 0), 3 BAD_INPUT (non-finite coordinate), 255 FRAGILE (a corner sign is
+ * not certified by tau_c, or a scale outside the guard: the exact tier
+ * decides).  quality: NaN for BAD_INPUT and outside the guard range. */
+static int corner_test_one(const double p[8][3], double* quality)
+{
+    *quality = NAN;
+    if (!all_finite(p)) return OV_BAD_INPUT;
+    Hex h;
+    hex_setup(p, &h);
+    const double tc = 24.0 * U64 * h.M;
+    int certain_pos = 1, certain_neg = 0;
+    double q = INFINITY;
+    for (int c = 0; c < 8; ++c) {
+        const int i = CORNER[c][0], j = CORNER[c][1], k = CORNER[c][2];
+        const double J = jacobian(&h, i, j, k);
+        if (J <= -tc) certain_neg = 1;
+        if (!(J > tc)) certain_pos = 0;
+        const double* a = h.ex[j + 2 * k];
+        const double* b = h.ey[i + 2 * k];
+        const double* z = h.ez[i + 2 * j];
+        const double den = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]) *
+                           sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]) *
+                           sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
+        q = fmin(q, den > 0.0 ? J / den : 0.0);
+    }
+    if (!h.in_range) return OV_FRAGILE;
+    *quality = q;
+    if (certain_neg) return OV_INVALID;
+    if (certain_pos) return OV_VALID;
+    return OV_FRAGILE;
+}
+
+/* Test 1 and corner quality of n hexahedra (layout as in oracle_check).
+ * Returns the number of FRAGILE elements. */
+int64_t oracle_corner_test(const double* pts, const int32_t* conn, int64_t n, int nthreads, uint8_t* test1,
+                           double* quality)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int64_t fragile = 0;
+#pragma omp parallel for schedule(static) reduction(+ : fragile)
+    for (int64_t e = 0; e < n; ++e) {
+        double p[8][3];
+        gather(pts, conn, e, p);
+        const int v = corner_test_one(p, quality + e);
+        test1[e] = (uint8_t)v;
+        if (v == OV_FRAGILE) fragile++;
+    }
+    return fragile;
+}
