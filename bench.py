@@ -282,6 +282,44 @@ def min_jacobian_leg(hx, torch, V, C, pts, conn, steps, stream, rtol=1e-3):
                        "disjoint_intervals_vs_gpu": disjoint}}
 
 
+def corner_test_leg(hx, torch, synth, steps, n_pool=16_000_000):
+    """The false-valid accounting of Section 7 (Table 4's methodology) on
+    synthetic data: a pool of independent tangled hexes (unit cube corners +
+    U(-0.6, 0.6)^3, seed 6) split, as the paper's datasets are, by a minimal
+    corner quality q in {0.5, 0, -1}; for each subset, the number of invalid
+    elements (full method), the corner-only test's false valid and false
+    invalid counts, and the device time of both."""
+    P = torch.from_numpy(synth.independent_hexes(n_pool, noise=0.6, seed=6)).to("cuda")
+    _, q, _ = hx.corner_test(P)
+    rows = []
+    for qmin in (0.5, 0.0, -1.0):
+        sub = P[q >= qmin].contiguous()
+        n = sub.shape[0]
+        mesh = hx.make_mesh(sub, None, n)
+        v = torch.empty(n, dtype=torch.uint8, device="cuda")
+        t1 = torch.empty_like(v)
+        opts = hx.make_opts(stream=torch.cuda.current_stream())
+        times = {}
+        for name, call in (("full", lambda: hx.hexval_check_ex(mesh, opts, v, None)),
+                           ("test1", lambda: hx.hexval_corner_test(mesh, opts, t1, None))):
+            call()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                call()
+            torch.cuda.synchronize()
+            times[name] = (time.perf_counter() - t0) / steps
+        inv = v == hx.INVALID
+        rows.append({"q_min": qmin, "hexes": n, "invalid": int(inv.sum()),
+                     "undecided": int((v == hx.UNDECIDED).sum()),
+                     "test1_false_valid": int((inv & (t1 == hx.VALID)).sum()),
+                     "test1_false_invalid": int(((v == hx.VALID) & (t1 == hx.INVALID)).sum()),
+                     "ms_full": 1e3 * times["full"], "ms_test1": 1e3 * times["test1"]})
+        del sub, v, t1
+    return {"workload": f"{n_pool} independent hexes, unit cube + U(-0.6,0.6)^3, split by min corner "
+                        "quality as Table 4's datasets", "rows": rows}
+
+
 def copy_calibration(torch, nbytes=1 << 30):
     """A plain device copy of known size, for scaling the profiler's
     FETCH_SIZE / WRITE_SIZE counters."""
@@ -379,6 +417,10 @@ def main():
         torch.cuda.empty_cache()
         out["fp32_filter_vs_fp64"] = fp32_leg(hx, torch, synth, max(5, args.steps // 2), stream)
         log(f"fp32 leg {out['fp32_filter_vs_fp64']}")
+        torch.cuda.empty_cache()
+        log("corner-only test leg")
+        out["corner_test_vs_full"] = corner_test_leg(hx, torch, synth, 5)
+        log(f"corner leg {out['corner_test_vs_full']}")
         torch.cuda.empty_cache()
         log("batched leg")
         out["batched"] = batched_leg(hx, torch, synth, 3)

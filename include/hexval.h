@@ -161,6 +161,27 @@ int hexval_check_batched(const hexval_mesh_t* meshes, int32_t n_meshes,
  */
 int hexval_coefficients(const hexval_mesh_t* mesh, void* stream, double* coeffs);
 
+/* ---- corner-only test and corner quality ------------------------------------
+ * hexval_corner_test: Test 1 of the comparison in Section 7 (the volumes of
+ * the 8 corner tetrahedra, i.e. the 8 corner values of J = the corner
+ * coefficients b_1..b_8, must all be positive) and the corner quality quoted
+ * for Fig. 7 (minimum over the corners of the scaled Jacobian
+ * J_c / (|e_xi| |e_eta| |e_zeta|), e_* the three edge vectors leaving corner
+ * c; a corner with a zero-length edge counts as 0).  The test is a necessary
+ * condition of validity: it can pass invalid elements ("false valid"), never
+ * fail valid ones; comparing it with hexval_check counts what the Bezier test
+ * adds.  Signs are exact (certified FP64, else integer arithmetic).
+ * mesh: as for hexval_check_ex.  opts: validate_indices, stream, stats (NULL =
+ *   defaults; precision and depth are not used).
+ * test1: device [n] uint8: HEXVAL_VALID (all 8 corner values > 0),
+ *   HEXVAL_INVALID, HEXVAL_BAD_INPUT.
+ * quality: device [n] float64 or NULL; NaN for BAD_INPUT and for elements
+ *   whose per-direction edge scales leave [2^-300, 2^300].
+ * Returns when the outputs are final.
+ */
+int hexval_corner_test(const hexval_mesh_t* mesh, const hexval_opts_t* opts, uint8_t* test1,
+                       double* quality);
+
 /* ---- minimum of the Jacobian determinant to a tolerance --------------------
  * The bounds of Section 3.1, sharpened by subdivision (the method the
  * introduction recalls, which computes min J to any prescribed tolerance): on

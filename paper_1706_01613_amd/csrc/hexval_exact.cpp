@@ -234,7 +234,10 @@ struct Tree {
 
 }  // namespace
 
-uint8_t exact_verdict(const double pts[24], int max_depth)
+// The 8 points as integers: every coordinate is m 2^e, so all are integer
+// multiples of 2^E, E the smallest such exponent.  Returns 3 for a non-finite
+// coordinate, 0 when every coordinate is 0 (one point: J = 0), else -1.
+static int integer_points(const double pts[24], BV p[8])
 {
     int emin = 0;
     bool any = false;
@@ -248,8 +251,7 @@ uint8_t exact_verdict(const double pts[24], int max_depth)
             any = true;
         }
     }
-    if (!any) return 0;   // all points coincide: J = 0 -> INVALID
-    BV p[8];
+    if (!any) return 0;
     for (int k = 0; k < 8; ++k) {
         Big c[3];
         for (int d = 0; d < 3; ++d) {
@@ -262,6 +264,30 @@ uint8_t exact_verdict(const double pts[24], int max_depth)
         }
         p[k] = {c[0], c[1], c[2]};
     }
+    return -1;
+}
+
+uint8_t exact_corner_test(const double pts[24])
+{
+    BV p[8];
+    const int pre = integer_points(pts, p);
+    if (pre >= 0) return (uint8_t)pre;
+    const BV a00 = bsub(p[1], p[0]), a10 = bsub(p[2], p[3]), a01 = bsub(p[5], p[4]), a11 = bsub(p[6], p[7]);
+    const BV b00 = bsub(p[3], p[0]), b10 = bsub(p[2], p[1]), b01 = bsub(p[7], p[4]), b11 = bsub(p[6], p[5]);
+    const BV c00 = bsub(p[4], p[0]), c10 = bsub(p[5], p[1]), c01 = bsub(p[7], p[3]), c11 = bsub(p[6], p[2]);
+    const Big J[8] = {triple(a00, b00, c00), triple(a00, b10, c10), triple(a10, b10, c11),
+                      triple(a10, b00, c01), triple(a01, b01, c00), triple(a01, b11, c10),
+                      triple(a11, b11, c11), triple(a11, b01, c01)};
+    for (const Big& v : J)
+        if (v.sign <= 0) return 0;
+    return 1;
+}
+
+uint8_t exact_verdict(const double pts[24], int max_depth)
+{
+    BV p[8];
+    const int pre = integer_points(pts, p);
+    if (pre >= 0) return (uint8_t)pre;   // 0: all points coincide, J = 0 -> INVALID
     const BV a00 = bsub(p[1], p[0]), a10 = bsub(p[2], p[3]), a01 = bsub(p[5], p[4]), a11 = bsub(p[6], p[7]);
     const BV b00 = bsub(p[3], p[0]), b10 = bsub(p[2], p[1]), b01 = bsub(p[7], p[4]), b11 = bsub(p[6], p[5]);
     const BV c00 = bsub(p[4], p[0]), c10 = bsub(p[5], p[1]), c01 = bsub(p[7], p[3]), c11 = bsub(p[6], p[2]);

@@ -922,6 +922,133 @@ __global__ __launch_bounds__(256) void k_minj_fold(MinjArgs a)
     }
 }
 
+// ================================================= corner-only test
+//
+// Test 1 of the comparison in Section 7: the element passes when its 8
+// corner values of J (the corner coefficients b_1..b_8, 6 x the volumes of
+// the corner tetrahedra) are all positive.  It is a necessary condition of
+// validity.  Signs are certified with the value bound (kTauValue u M^);
+// elements whose signs are not certified, or whose scales leave the guard
+// range, go to the exact tier.  Corner quality: the minimum over the corners
+// of J_c / (|e_xi| |e_eta| |e_zeta|), the three edge vectors leaving the
+// corner (a corner with a zero-length edge counts as 0); NaN for bad input
+// and outside the guard range.
+
+__device__ __forceinline__ double norm3(const W3<double>& v)
+{
+    return sqrt(v.x * v.x + v.y * v.y + v.z * v.z);
+}
+
+__global__ __launch_bounds__(256) void k_corner_test(CornerArgs a)
+{
+    const MeshDev& m = a.mesh;
+    const QueueDev& q = a.q;
+    TileSched ts(a.n_tiles, a.xcds, q.cnt);
+    for (int64_t t = ts.next_tile(); t >= 0; t = ts.next_tile()) {
+        const int64_t e = t * (int64_t)blockDim.x + threadIdx.x;
+        const bool active = e < m.n;
+        uint8_t v = 0;
+        double qual = __builtin_nan("");
+        bool exact = false;
+        if (active) {
+            V3 p[8];
+            bool bad = false;
+            load_points(m, e, p, bad);
+            if (bad) {
+                v = 3;
+            } else {
+                typedef W3<double> E;
+                const E a00 = edge_t<double>(p[1], p[0]), a10 = edge_t<double>(p[2], p[3]);
+                const E a01 = edge_t<double>(p[5], p[4]), a11 = edge_t<double>(p[6], p[7]);
+                const E b00 = edge_t<double>(p[3], p[0]), b10 = edge_t<double>(p[2], p[1]);
+                const E b01 = edge_t<double>(p[7], p[4]), b11 = edge_t<double>(p[6], p[5]);
+                const E c00 = edge_t<double>(p[4], p[0]), c10 = edge_t<double>(p[5], p[1]);
+                const E c01 = edge_t<double>(p[7], p[3]), c11 = edge_t<double>(p[6], p[2]);
+                const double sx = fmax(fmax(amax_t(fabs(a00.x), a10), amax_t(fabs(a00.y), a01)), amax_t(fabs(a00.z), a11));
+                const double sy = fmax(fmax(amax_t(fabs(b00.x), b10), amax_t(fabs(b00.y), b01)), amax_t(fabs(b00.z), b11));
+                const double sz = fmax(fmax(amax_t(fabs(c00.x), c10), amax_t(fabs(c00.y), c01)), amax_t(fabs(c00.z), c11));
+                // corner (i,j,k): xi-edge a_jk, eta-edge b_ik, zeta-edge c_ij
+                const double J[8] = {triple_t(a00, b00, c00), triple_t(a00, b10, c10), triple_t(a10, b10, c11),
+                                     triple_t(a10, b00, c01), triple_t(a01, b01, c00), triple_t(a01, b11, c10),
+                                     triple_t(a11, b11, c11), triple_t(a11, b01, c01)};
+                bool finite = true;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) finite = finite && isfinite(J[k]);
+                const bool in_range = sx >= Guard<double>::lo && sx <= Guard<double>::hi && sy >= Guard<double>::lo &&
+                                      sy <= Guard<double>::hi && sz >= Guard<double>::lo && sz <= Guard<double>::hi;
+                if (!finite) {
+                    bool coords = true;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        coords = coords && isfinite(p[k].x) && isfinite(p[k].y) && isfinite(p[k].z);
+                    if (coords) exact = true;   // overflow of a finite input: outside the guard
+                    else v = 3;
+                } else if (!in_range) {
+                    exact = true;
+                } else {
+                    const double tau = kTauValue * kU64 * ((6.0 * sx) * sy * sz);
+                    bool neg = false, pos = true;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        neg = neg || J[k] <= -tau;
+                        pos = pos && J[k] > tau;
+                    }
+                    if (neg) v = 0;
+                    else if (pos) v = 1;
+                    else exact = true;
+                    const double na[4] = {norm3(a00), norm3(a10), norm3(a01), norm3(a11)};
+                    const double nb[4] = {norm3(b00), norm3(b10), norm3(b01), norm3(b11)};
+                    const double nc[4] = {norm3(c00), norm3(c10), norm3(c01), norm3(c11)};
+                    qual = HUGE_VAL;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const int i = k == 1 || k == 2 || k == 5 || k == 6;
+                        const int j = k == 2 || k == 3 || k == 6 || k == 7;
+                        const int l = k >= 4;
+                        const double den = na[j + 2 * l] * nb[i + 2 * l] * nc[i + 2 * j];
+                        qual = fmin(qual, den > 0.0 ? J[k] / den : 0.0);
+                    }
+                }
+            }
+        }
+        const uint64_t xmask = ballot(exact);
+        if (xmask) {
+            const unsigned long long slot = wave_reserve(&q.cnt->n_exact, xmask);
+            if (exact && slot < q.exact_cap) {
+                q.exact_elem[slot] = e;
+                q.exact_mesh[slot] = 0;
+            }
+        }
+        if (exact) v = kExact;   // pending: settled by the exact tier
+        if (active) {
+            m.verdict[e] = v;
+            if (a.quality) a.quality[e] = qual;
+        }
+    }
+}
+
+// Lists pending elements into the exact list (up to its capacity), for the
+// rounds after the first when more were pending than it holds.  Whole waves
+// iterate together.
+__global__ __launch_bounds__(256) void k_corner_collect(CornerArgs a)
+{
+    const MeshDev& m = a.mesh;
+    const QueueDev& q = a.q;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e0 = blockIdx.x * (int64_t)blockDim.x; e0 < m.n; e0 += stride) {
+        const int64_t e = e0 + threadIdx.x;
+        const bool pend = e < m.n && m.verdict[e] == kExact;
+        const uint64_t mask = ballot(pend);
+        if (mask) {
+            const unsigned long long slot = wave_reserve(&q.cnt->n_exact, mask);
+            if (pend && slot < q.exact_cap) {
+                q.exact_elem[slot] = e;
+                q.exact_mesh[slot] = 0;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------ small kernels
 
 __global__ void k_reset(Counters* c)
@@ -1075,6 +1202,8 @@ void launch_scatter_exact(const ScatterArgs& a, hipStream_t s)
     const int64_t g = (a.n + 255) / 256;
     HX_LAUNCH(k_scatter_exact, g < 1024 ? g : 1024, 256, s, a);
 }
+void launch_corner_test(const CornerArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_corner_test, grid, 256, s, a); }
+void launch_corner_collect(const CornerArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_corner_collect, grid, 256, s, a); }
 void launch_minj_top(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_top, grid, 256, s, a); }
 void launch_minj_roots(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_roots, grid, 256, s, a); }
 void launch_minj_level(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_level, grid, 256, s, a); }

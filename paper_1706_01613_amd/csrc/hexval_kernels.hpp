@@ -86,6 +86,18 @@ struct MinjArgs {
     int32_t xcds;
 };
 
+// Corner-only test and corner quality (hexval_corner_test).
+struct CornerArgs {
+    QueueDev q;
+    MeshDev mesh;        // mesh.verdict = the test1 output
+    double* quality;     // [n] or nullptr
+    int64_t n_tiles;
+    int32_t xcds;
+};
+
+void launch_corner_test(const CornerArgs& a, int grid, hipStream_t s);
+void launch_corner_collect(const CornerArgs& a, int grid, hipStream_t s);
+
 void launch_minj_top(const MinjArgs& a, int grid, hipStream_t s);
 void launch_minj_roots(const MinjArgs& a, int grid, hipStream_t s);
 void launch_minj_level(const MinjArgs& a, int grid, hipStream_t s);

@@ -337,7 +337,9 @@ static uint64_t pow2_ceil(uint64_t x)
 
 // ---------------------------------------------------------------- exact tier
 
-static void run_exact_host(const double* pts, uint8_t* out, int64_t n, int max_depth)
+// Exact tier on host threads: the verdict of each element, or with
+// corner_only the corner-only test.
+static void run_exact_host(const double* pts, uint8_t* out, int64_t n, int max_depth, bool corner_only = false)
 {
     if (n <= 0) return;
     const int64_t nt = std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()), 16);
@@ -347,7 +349,8 @@ static void run_exact_host(const double* pts, uint8_t* out, int64_t n, int max_d
         const int64_t lo = t * per, hi = std::min(n, lo + per);
         if (lo >= hi) break;
         th.emplace_back([=] {
-            for (int64_t i = lo; i < hi; ++i) out[i] = exact_verdict(pts + 24 * i, max_depth);
+            for (int64_t i = lo; i < hi; ++i)
+                out[i] = corner_only ? exact_corner_test(pts + 24 * i) : exact_verdict(pts + 24 * i, max_depth);
         });
     }
     for (auto& x : th) x.join();
@@ -355,9 +358,9 @@ static void run_exact_host(const double* pts, uint8_t* out, int64_t n, int max_d
 
 // ---------------------------------------------------------------- autotuner
 // Launch shape of the first-pass kernel: threads per block (= elements per
-// tile) and grid (one tile per block, or a persistent grid of k blocks per
-// CU striding over the tiles).  Picked by timing every candidate once on the
-// call's own input (after one untimed run), cached per (device architecture,
+// tile) and a persistent grid of k blocks per CU (4, 8, 16 or 32) taking
+// tiles at run time.  Picked by timing every candidate twice on the call's
+// own input (the better time counts), cached per (device architecture,
 // precision, gather mode, batched, log2 size bucket) and optionally
 // persisted in the file named by HEXVAL_TUNE_CACHE.  The per-element
 // arithmetic never depends on the launch shape.
@@ -823,6 +826,88 @@ int run_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts_in, do
     return HEXVAL_OK;
 }
 
+// Corner-only test and corner quality: one pass, then the exact tier for the
+// elements whose corner signs are not certified (in batches of the exact
+// list's capacity).
+int run_corner_test(const hexval_mesh_t* mesh, const hexval_opts_t* opts_in, uint8_t* test1, double* quality)
+{
+    hexval_opts_t o;
+    if (opts_in) o = *opts_in;
+    else default_opts(&o);
+    int rc = check_opts(&o);
+    if (rc) return rc;
+    if (!mesh) return fail(HEXVAL_E_ARG, "mesh is NULL");
+    if ((rc = check_mesh(mesh, test1, o.validate_indices, 0))) return rc;
+    hexval_stats_t* st = o.stats;
+    if (st) {
+        const int timing = st->timing;
+        memset(st, 0, sizeof *st);
+        st->timing = timing;
+    }
+    const int64_t n = mesh->n;
+    if (n == 0) return HEXVAL_OK;
+    int dev, cus;
+    if ((rc = current_device(&dev, &cus))) return rc;
+    hipStream_t s = (hipStream_t)o.stream;
+    WorkspaceGuard wg;
+    if ((rc = acquire_workspace(dev, &wg.w))) return rc;
+    Workspace& w = *wg.w;
+    if ((rc = w.ensure(0, 0, 1, 1))) return rc;
+    CornerArgs a{};
+    a.q = w.queue();
+    a.mesh.points = mesh->points;
+    a.mesh.conn = mesh->connectivity;
+    a.mesh.n = n;
+    a.mesh.n_points = mesh->n_points;
+    a.mesh.validate = (o.validate_indices && mesh->connectivity) ? 1 : 0;
+    a.mesh.verdict = test1;
+    a.quality = quality;
+    a.n_tiles = (n + 255) / 256;
+    a.xcds = 8;
+    const bool timing = st && st->timing;
+    launch_reset(w.cnt, s);
+    if (timing) HX_HIP(hipEventRecord(w.ev[0], s));
+    launch_corner_test(a, cus * 16, s);
+    if (timing) HX_HIP(hipEventRecord(w.ev[1], s));
+    HX_HIP(hipGetLastError());
+    HX_HIP(hipMemcpyAsync(w.hcnt, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    HX_HIP(hipStreamSynchronize(s));
+    uint64_t pending = w.hcnt->n_exact, settled = 0;
+    while (pending > 0) {
+        const int64_t k = (int64_t)std::min<uint64_t>(pending, w.exact_cap);
+        GatherArgs ga{a.q, a.mesh, nullptr, k, w.exact_pts};
+        launch_gather_exact(ga, s);
+        HX_HIP(hipMemcpyAsync(w.h_exact_pts, w.exact_pts, k * 24 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HX_HIP(hipStreamSynchronize(s));
+        run_exact_host(w.h_exact_pts, w.h_exact_v, k, 0, true);
+        HX_HIP(hipMemcpyAsync(w.exact_v, w.h_exact_v, k, hipMemcpyHostToDevice, s));
+        MeshDev sm = a.mesh;
+        sm.min_coeff = nullptr;
+        ScatterArgs sa{a.q, sm, nullptr, k, w.exact_v};
+        launch_scatter_exact(sa, s);
+        settled += (uint64_t)k;
+        if (pending == (uint64_t)k) break;
+        launch_reset(w.cnt, s);
+        launch_corner_collect(a, cus * 8, s);
+        HX_HIP(hipGetLastError());
+        HX_HIP(hipMemcpyAsync(w.hcnt, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HX_HIP(hipStreamSynchronize(s));
+        pending = w.hcnt->n_exact;
+    }
+    if (timing) HX_HIP(hipEventRecord(w.ev[2], s));
+    HX_HIP(hipStreamSynchronize(s));
+    if (st) {
+        st->n_elements = n;
+        st->n_exact = (int64_t)settled;
+        st->n_rounds = 1;
+        if (timing) {
+            hipEventElapsedTime(&st->ms_first_pass, w.ev[0], w.ev[1]);
+            hipEventElapsedTime(&st->ms_total, w.ev[0], w.ev[2]);
+        }
+    }
+    return HEXVAL_OK;
+}
+
 int run_coefficients(const hexval_mesh_t* mesh, void* stream, double* coeffs)
 {
     if (!mesh) return fail(HEXVAL_E_ARG, "mesh is NULL");
@@ -861,6 +946,11 @@ int hexval_check(const double* points, const int32_t* connectivity, int64_t n, u
 {
     hexval_mesh_t m{points, 0, connectivity, n};
     return run_check(&m, 1, false, nullptr, &verdicts, &min_coeffs);
+}
+
+int hexval_corner_test(const hexval_mesh_t* mesh, const hexval_opts_t* opts, uint8_t* test1, double* quality)
+{
+    return run_corner_test(mesh, opts, test1, quality);
 }
 
 int hexval_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts, double rtol, double* lo, double* hi,

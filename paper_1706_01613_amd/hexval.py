@@ -77,6 +77,8 @@ def lib():
             "hexval_check_batched": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t), I32,
                                                     ctypes.POINTER(hexval_opts_t), P, P]),
             "hexval_coefficients": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t), P, P]),
+            "hexval_corner_test": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t),
+                                                  ctypes.POINTER(hexval_opts_t), P, P]),
             "hexval_min_jacobian": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t),
                                                    ctypes.POINTER(hexval_opts_t), ctypes.c_double,
                                                    P, P, P]),
@@ -179,6 +181,12 @@ def hexval_coefficients(mesh, stream, coeffs):
     return _check(lib().hexval_coefficients(ctypes.byref(mesh), _stream_handle(stream), _addr(coeffs)))
 
 
+def hexval_corner_test(mesh, opts, test1, quality=None):
+    """C: hexval_corner_test."""
+    return _check(lib().hexval_corner_test(ctypes.byref(mesh), ctypes.byref(opts) if opts else None,
+                                           _addr(test1), _addr(quality)))
+
+
 def hexval_min_jacobian(mesh, opts, rtol, lo, hi, status=None):
     """C: hexval_min_jacobian."""
     return _check(lib().hexval_min_jacobian(ctypes.byref(mesh), ctypes.byref(opts) if opts else None,
@@ -269,3 +277,20 @@ def min_jacobian(points, connectivity=None, rtol=1e-3, max_depth=6, validate_ind
     opts = make_opts(FP64, max_depth, validate_indices, 0, queue_capacity, 0, stream, st)
     hexval_min_jacobian(make_mesh(points, connectivity, n), opts, rtol, lo, hi, status)
     return lo, hi, status, (st.as_dict() if stats else None)
+
+
+def corner_test(points, connectivity=None, validate_indices=False, stream=None, stats=False,
+                want_quality=True):
+    """Allocate outputs and run hexval_corner_test.  Returns (test1 uint8,
+    quality float64 or None, stats dict or None) on points' device."""
+    import torch
+    n = connectivity.shape[0] if connectivity is not None else points.shape[0]
+    test1 = torch.empty(n, dtype=torch.uint8, device=points.device)
+    quality = torch.empty(n, dtype=torch.float64, device=points.device) if want_quality else None
+    st = hexval_stats_t()
+    st.timing = 1 if stats else 0
+    if stream is None:
+        stream = torch.cuda.current_stream(points.device)
+    opts = make_opts(FP64, 6, validate_indices, 0, 0, 0, stream, st)
+    hexval_corner_test(make_mesh(points, connectivity, n), opts, test1, quality)
+    return test1, quality, (st.as_dict() if stats else None)
