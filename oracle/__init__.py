@@ -50,6 +50,8 @@ def _load():
         lib.oracle_T.argtypes = [P]
         lib.oracle_bound_constants.restype = None
         lib.oracle_bound_constants.argtypes = [P]
+        lib.oracle_quad_check.restype = ctypes.c_int64
+        lib.oracle_quad_check.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, P, P]
         lib.oracle_corner_test.restype = ctypes.c_int64
         lib.oracle_corner_test.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, P, P]
         lib.oracle_min_jacobian.restype = None
@@ -143,6 +145,31 @@ def corner_test(points, conn=None, threads=0):
     for e in fragile:
         test1[e] = exact.corner_test(element_points(points, conn, e))
     return dict(test1=test1, quality=quality, fragile=fragile)
+
+
+def quad_check(points, conn=None, threads=0):
+    """Validity of linear quadrangles (Section 2.1): INVALID when a corner
+    value of J is <= 0, VALID when all four are > 0; uncertified signs are
+    settled exactly.  points: [n,4,2], or [m,2] with conn [n,4] int32.
+    Returns a dict with ``verdict`` (uint8 [n]), ``min_j`` (float64 [n]: the
+    smallest corner value, which is min J) and ``fragile``."""
+    lib = _load()
+    points = np.ascontiguousarray(points, dtype=np.float64)
+    if conn is None:
+        points = points.reshape(-1, 4, 2)
+        n = points.shape[0]
+    else:
+        conn = np.ascontiguousarray(conn, dtype=np.int32).reshape(-1, 4)
+        points = points.reshape(-1, 2)
+        n = conn.shape[0]
+    verdict = np.empty(n, np.uint8)
+    min_j = np.empty(n, np.float64)
+    lib.oracle_quad_check(_ptr(points), _ptr(conn), n, int(threads), _ptr(verdict), _ptr(min_j))
+    fragile = np.nonzero(verdict == FRAGILE)[0]
+    for e in fragile:
+        q = points[e] if conn is None else points[conn[e]]
+        verdict[e] = exact.quad_validity(q)
+    return dict(verdict=verdict, min_j=min_j, fragile=fragile)
 
 
 MJ_CONVERGED, MJ_CAPPED, MJ_BAD_INPUT, MJ_OUT_OF_RANGE = 0, 1, 3, 4

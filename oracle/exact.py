@@ -189,3 +189,20 @@ def corner_test(points):
         if jacobian(edges, Fraction(n[0], 2), Fraction(n[1], 2), Fraction(n[2], 2)) <= 0:
             return INVALID
     return VALID
+
+
+def quad_validity(points):
+    """Linear quadrangle (Section 2.1) in exact arithmetic: the Jacobian matrix
+    of the bilinear map at each corner, VALID when all four determinants are
+    > 0, else INVALID (BAD_INPUT for a non-finite coordinate)."""
+    P = []
+    for p in points:
+        if not all(math.isfinite(float(v)) for v in p):
+            return BAD_INPUT
+        P.append((Fraction(float(p[0])), Fraction(float(p[1]))))
+    for xi, eta in ((0, 0), (1, 0), (1, 1), (0, 1)):
+        X = [(P[1][d] - P[0][d]) * (1 - eta) + (P[2][d] - P[3][d]) * eta for d in range(2)]
+        Y = [(P[3][d] - P[0][d]) * (1 - xi) + (P[2][d] - P[1][d]) * xi for d in range(2)]
+        if X[0] * Y[1] - X[1] * Y[0] <= 0:
+            return INVALID
+    return VALID

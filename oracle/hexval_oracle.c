@@ -576,3 +576,81 @@ int64_t oracle_corner_test(const double* pts, const int32_t* conn, int64_t n, in
     }
     return fragile;
 }
+
+/* ---- linear quadrangles (Section 2.1) ---------------------------------------
+ *
+ * The bilinear map of [0,1]^2 with corners n1..n4 at (0,0) (1,0) (1,1) (0,1);
+ * its Jacobian matrix has columns x_xi = (n2-n1)(1-eta) + (n3-n4) eta and
+ * x_eta = (n4-n1)(1-xi) + (n3-n2) xi, and J = det[x_xi x_eta] is bilinear, so
+ * its minimum over the element is one of the four corner values.  Verdict:
+ * INVALID when a corner value is <= 0, VALID when all four are > 0 (the same
+ * strict reading as for hexahedra).  The corner values come from evaluating
+ * the Jacobian matrix at each corner (not from the per-corner cross products
+ * the paper writes out).  Error: each edge component is one rounded
+ * difference, each product adds one rounding and the difference one more, so
+ * |J^ - J| <= ((1+u)^3 - 1) 2 S^2 + u 2 S^2 (1 + 3.01 u) <= 8.001 u S^2, S the
+ * largest |component| of the four edge vectors; the threshold is 9 u S^2.
+ * min_j: the smallest corner value.  verdict 255 (FRAGILE): a sign not
+ * certified (or S outside [2^-450, 2^450]), settled exactly. */
+static int quad_one(const double p[4][2], double* min_j)
+{
+    for (int k = 0; k < 4; ++k)
+        if (!isfinite(p[k][0]) || !isfinite(p[k][1])) {
+            *min_j = NAN;
+            return OV_BAD_INPUT;
+        }
+    double ex0[2], ex1[2], ey0[2], ey1[2], s = 0.0;
+    for (int d = 0; d < 2; ++d) {
+        ex0[d] = p[1][d] - p[0][d];   /* eta = 0 */
+        ex1[d] = p[2][d] - p[3][d];   /* eta = 1 */
+        ey0[d] = p[3][d] - p[0][d];   /* xi = 0 */
+        ey1[d] = p[2][d] - p[1][d];   /* xi = 1 */
+        s = fmax(s, fmax(fmax(fabs(ex0[d]), fabs(ex1[d])), fmax(fabs(ey0[d]), fabs(ey1[d]))));
+    }
+    static const int XY[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+    double mn = INFINITY;
+    int neg = 0, pos = 1;
+    const double tau = 9.0 * U64 * s * s;
+    for (int k = 0; k < 4; ++k) {
+        const double xi = XY[k][0], eta = XY[k][1];
+        double X[2], Y[2];
+        for (int d = 0; d < 2; ++d) {
+            X[d] = ex0[d] * (1 - eta) + ex1[d] * eta;
+            Y[d] = ey0[d] * (1 - xi) + ey1[d] * xi;
+        }
+        const double J = X[0] * Y[1] - X[1] * Y[0];
+        mn = fmin(mn, J);
+        if (J <= -tau) neg = 1;
+        if (!(J > tau)) pos = 0;
+    }
+    *min_j = mn;
+    /* guard: s^2 must neither overflow nor lose the bound to underflow */
+    if (!(s >= ldexp(1.0, -450) && s <= ldexp(1.0, 450))) return OV_FRAGILE;
+    if (neg) return OV_INVALID;
+    if (pos) return OV_VALID;
+    return OV_FRAGILE;
+}
+
+/* Quadrangles: pts [n,4,2] when conn is NULL, else [*,2] indexed by conn [n,4]
+ * (corners in the order (0,0) (1,0) (1,1) (0,1)).  Returns #FRAGILE. */
+int64_t oracle_quad_check(const double* pts, const int32_t* conn, int64_t n, int nthreads, uint8_t* verdict,
+                          double* min_j)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int64_t fragile = 0;
+#pragma omp parallel for schedule(static) reduction(+ : fragile)
+    for (int64_t e = 0; e < n; ++e) {
+        double p[4][2];
+        for (int k = 0; k < 4; ++k) {
+            const double* q = conn ? pts + 2 * (int64_t)conn[4 * e + k] : pts + 8 * e + 2 * k;
+            p[k][0] = q[0];
+            p[k][1] = q[1];
+        }
+        const int v = quad_one(p, min_j + e);
+        verdict[e] = (uint8_t)v;
+        if (v == OV_FRAGILE) fragile++;
+    }
+    return fragile;
+}
