@@ -320,6 +320,36 @@ def corner_test_leg(hx, torch, synth, steps, n_pool=16_000_000):
                         "quality as Table 4's datasets", "rows": rows}
 
 
+def quad_leg(hx, torch, synth, steps, n=8000):
+    """Linear quadrangles (Section 2.1): n^2-cell warped lattice, 1% of the
+    vertices jittered 0.8 cell, int32 connectivity + f64 shared vertices
+    resident in HBM; verdicts and min J."""
+    V, C = synth.quad_lattice(n, n, seed=0)
+    pts, conn = torch.from_numpy(V).to("cuda"), torch.from_numpy(C).to("cuda")
+    nq = C.shape[0]
+    v = torch.empty(nq, dtype=torch.uint8, device="cuda")
+    m = torch.empty(nq, dtype=torch.float64, device="cuda")
+    st = hx.hexval_stats_t()
+    st.timing = 1
+    mesh = hx.hexval_mesh_t(pts.data_ptr(), V.shape[0], conn.data_ptr(), nq)
+    opts = hx.make_opts(stream=torch.cuda.current_stream(), stats=st)
+    hx.hexval_quad_check(mesh, opts, v, m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = []
+    for _ in range(steps):
+        hx.hexval_quad_check(mesh, opts, v, m)
+        ms.append(st.ms_first_pass)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    alg = 16 * nq + 16 * V.shape[0] + 9 * nq
+    k = float(np.mean(ms))
+    return {"workload": f"{n}^2 warped quad lattice, 1% of vertices jittered 0.8 cell", "quads": nq,
+            "value": nq / wall, "unit": "quad/s", "ms_per_step": 1e3 * wall, "ms_kernel": k,
+            "algorithmic_GBps": alg / (k * 1e-3) / 1e9,
+            "invalid": int((v == hx.INVALID).sum()), "stats": st.as_dict()}
+
+
 def copy_calibration(torch, nbytes=1 << 30):
     """A plain device copy of known size, for scaling the profiler's
     FETCH_SIZE / WRITE_SIZE counters."""
@@ -417,6 +447,10 @@ def main():
         torch.cuda.empty_cache()
         out["fp32_filter_vs_fp64"] = fp32_leg(hx, torch, synth, max(5, args.steps // 2), stream)
         log(f"fp32 leg {out['fp32_filter_vs_fp64']}")
+        torch.cuda.empty_cache()
+        log("quad leg")
+        out["quads"] = quad_leg(hx, torch, synth, 10)
+        log(f"quad leg {out['quads']}")
         torch.cuda.empty_cache()
         log("corner-only test leg")
         out["corner_test_vs_full"] = corner_test_leg(hx, torch, synth, 5)

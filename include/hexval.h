@@ -182,6 +182,25 @@ int hexval_coefficients(const hexval_mesh_t* mesh, void* stream, double* coeffs)
 int hexval_corner_test(const hexval_mesh_t* mesh, const hexval_opts_t* opts, uint8_t* test1,
                        double* quality);
 
+/* ---- linear quadrangles -------------------------------------------------------
+ * hexval_quad_check: validity of linear quadrangles (Section 2.1).  The map of
+ * [0,1]^2 is bilinear, so is J, and its minimum over the element is one of
+ * the four corner values; the element is VALID when all four are > 0 and
+ * INVALID otherwise (same strict reading as for hexahedra).  Signs are exact
+ * (certified FP64, else integer arithmetic).
+ * mesh: points device float64, [n,4,2] when connectivity is NULL, else
+ *   [n_points,2] with connectivity device [n,4] int32; corners in the order
+ *   (0,0) (1,0) (1,1) (0,1) of the reference square (counter-clockwise for a
+ *   valid element in a right-handed plane); rows 16-byte aligned.
+ * opts: validate_indices, stream, stats (NULL = defaults).
+ * verdicts: device [n] uint8 (HEXVAL_INVALID, HEXVAL_VALID, HEXVAL_BAD_INPUT).
+ * min_j: device [n] float64 or NULL: min J = the smallest corner value
+ *   (FP64; NaN for BAD_INPUT).
+ * Returns when the outputs are final.
+ */
+int hexval_quad_check(const hexval_mesh_t* mesh, const hexval_opts_t* opts, uint8_t* verdicts,
+                      double* min_j);
+
 /* ---- minimum of the Jacobian determinant to a tolerance --------------------
  * The bounds of Section 3.1, sharpened by subdivision (the method the
  * introduction recalls, which computes min J to any prescribed tolerance): on

@@ -283,6 +283,44 @@ uint8_t exact_corner_test(const double pts[24])
     return 1;
 }
 
+uint8_t exact_quad(const double pts[8])
+{
+    // the 2D points as integers (as integer_points does in 3D)
+    int emin = 0;
+    bool any = false;
+    for (int i = 0; i < 8; ++i) {
+        if (!isfinite(pts[i])) return 3;
+        if (pts[i] != 0.0) {
+            int e;
+            frexp(pts[i], &e);
+            if (!any || e - 53 < emin) emin = e - 53;
+            any = true;
+        }
+    }
+    if (!any) return 0;
+    Big x[4], y[4];
+    for (int k = 0; k < 4; ++k)
+        for (int d = 0; d < 2; ++d) {
+            const double v = pts[2 * k + d];
+            if (v == 0.0) continue;
+            int e;
+            const double f = frexp(fabs(v), &e);
+            (d == 0 ? x[k] : y[k]) = Big::from_shifted((uint64_t)ldexp(f, 53), (e - 53) - emin, v < 0);
+        }
+    // Jacobian matrix of the bilinear map at corner (xi, eta): columns
+    // x_xi = n2-n1 (eta 0) or n3-n4 (eta 1), x_eta = n4-n1 (xi 0) or n3-n2 (xi 1)
+    static const int XI[2][2] = {{1, 0}, {2, 3}}, ETA[2][2] = {{3, 0}, {2, 1}};
+    static const int C[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+    for (const auto& c : C) {
+        const int* a = XI[c[1]];
+        const int* b = ETA[c[0]];
+        const Big J = sub(mul(sub(x[a[0]], x[a[1]]), sub(y[b[0]], y[b[1]])),
+                          mul(sub(y[a[0]], y[a[1]]), sub(x[b[0]], x[b[1]])));
+        if (J.sign <= 0) return 0;
+    }
+    return 1;
+}
+
 uint8_t exact_verdict(const double pts[24], int max_depth)
 {
     BV p[8];

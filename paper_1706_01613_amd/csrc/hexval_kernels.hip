@@ -1049,6 +1049,111 @@ __global__ __launch_bounds__(256) void k_corner_collect(CornerArgs a)
     }
 }
 
+// ================================================ linear quadrangles
+//
+// Section 2.1: the bilinear map of [0,1]^2 (corners at (0,0) (1,0) (1,1)
+// (0,1)) has a bilinear J, whose minimum is one of the four corner values
+// J = det[x_xi x_eta] at the corner.  Signs are certified with 9 u S^2 (S the
+// largest |component| of the four edge vectors, in [2^-450, 2^450]); other
+// elements go to the exact tier.  min_j: the smallest corner value.
+
+__device__ __forceinline__ void load_quad(const MeshDev& m, int64_t e, double2 p[4], bool& bad)
+{
+    if (m.conn) {
+        const int4 c = *reinterpret_cast<const int4*>(m.conn + 4 * e);
+        const int idx[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (m.validate && (idx[k] < 0 || (int64_t)idx[k] >= m.n_points)) bad = true;
+        }
+        if (bad) return;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) p[k] = *reinterpret_cast<const double2*>(m.points + 2 * (int64_t)idx[k]);
+    } else {
+        const double2* v = reinterpret_cast<const double2*>(m.points + 8 * e);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) p[k] = v[k];
+    }
+}
+
+__device__ __forceinline__ double cross2(double ax, double ay, double bx, double by)
+{
+    return fma(ax, by, -(ay * bx));
+}
+
+__global__ __launch_bounds__(256) void k_quad_check(CornerArgs a)
+{
+    const MeshDev& m = a.mesh;
+    const QueueDev& q = a.q;
+    TileSched ts(a.n_tiles, a.xcds, q.cnt);
+    for (int64_t t = ts.next_tile(); t >= 0; t = ts.next_tile()) {
+        const int64_t e = t * (int64_t)blockDim.x + threadIdx.x;
+        const bool active = e < m.n;
+        uint8_t v = 0;
+        double mn = __builtin_nan("");
+        bool exact = false;
+        if (active) {
+            double2 p[4];
+            bool bad = false;
+            load_quad(m, e, p, bad);
+            bool finite = !bad;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) finite = finite && isfinite(p[k].x) && isfinite(p[k].y);
+            if (!finite) {
+                v = 3;
+            } else {
+                // x_xi on eta = 0 and 1, x_eta on xi = 0 and 1
+                const double ax0 = p[1].x - p[0].x, ay0 = p[1].y - p[0].y;
+                const double ax1 = p[2].x - p[3].x, ay1 = p[2].y - p[3].y;
+                const double bx0 = p[3].x - p[0].x, by0 = p[3].y - p[0].y;
+                const double bx1 = p[2].x - p[1].x, by1 = p[2].y - p[1].y;
+                const double S = fmax(fmax(fmax(fabs(ax0), fabs(ay0)), fmax(fabs(ax1), fabs(ay1))),
+                                      fmax(fmax(fabs(bx0), fabs(by0)), fmax(fabs(bx1), fabs(by1))));
+                const double J0 = cross2(ax0, ay0, bx0, by0);   // (0,0)
+                const double J1 = cross2(ax0, ay0, bx1, by1);   // (1,0)
+                const double J2 = cross2(ax1, ay1, bx1, by1);   // (1,1)
+                const double J3 = cross2(ax1, ay1, bx0, by0);   // (0,1)
+                mn = fmin(fmin(J0, J1), fmin(J2, J3));
+                const double tau = 9.0 * kU64 * S * S;
+                const bool in_range = S >= 0x1p-450 && S <= 0x1p+450;
+                if (!in_range) exact = true;
+                else if (mn <= -tau) v = 0;
+                else if (mn > tau) v = 1;
+                else exact = true;
+            }
+        }
+        const uint64_t xmask = ballot(exact);
+        if (xmask) {
+            const unsigned long long slot = wave_reserve(&q.cnt->n_exact, xmask);
+            if (exact && slot < q.exact_cap) {
+                q.exact_elem[slot] = e;
+                q.exact_mesh[slot] = 0;
+            }
+        }
+        if (exact) v = kExact;
+        if (active) {
+            m.verdict[e] = v;
+            if (a.quality) a.quality[e] = mn;
+        }
+    }
+}
+
+// The 4 points (8 doubles) of each listed element, for the exact tier.
+__global__ void k_quad_gather(CornerArgs a, int64_t n, double* out)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double2 p[4];
+        bool bad = false;
+        load_quad(a.mesh, a.q.exact_elem[i], p, bad);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            out[8 * i + 2 * k] = p[k].x;
+            out[8 * i + 2 * k + 1] = p[k].y;
+        }
+    }
+}
+
 // ------------------------------------------------------------ small kernels
 
 __global__ void k_reset(Counters* c)
@@ -1204,6 +1309,12 @@ void launch_scatter_exact(const ScatterArgs& a, hipStream_t s)
 }
 void launch_corner_test(const CornerArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_corner_test, grid, 256, s, a); }
 void launch_corner_collect(const CornerArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_corner_collect, grid, 256, s, a); }
+void launch_quad_check(const CornerArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_quad_check, grid, 256, s, a); }
+void launch_quad_gather(const CornerArgs& a, int64_t n, double* out, hipStream_t s)
+{
+    const int64_t g = (n + 255) / 256;
+    HX_LAUNCH(k_quad_gather, g < 4096 ? g : 4096, 256, s, a, n, out);
+}
 void launch_minj_top(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_top, grid, 256, s, a); }
 void launch_minj_roots(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_roots, grid, 256, s, a); }
 void launch_minj_level(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_level, grid, 256, s, a); }

@@ -96,6 +96,10 @@ struct CornerArgs {
 };
 
 void launch_corner_test(const CornerArgs& a, int grid, hipStream_t s);
+// Linear quadrangles (hexval_quad_check): mesh.points are 2D, mesh.conn [n,4];
+// `quality` carries min_j.
+void launch_quad_check(const CornerArgs& a, int grid, hipStream_t s);
+void launch_quad_gather(const CornerArgs& a, int64_t n, double* out, hipStream_t s);
 void launch_corner_collect(const CornerArgs& a, int grid, hipStream_t s);
 
 void launch_minj_top(const MinjArgs& a, int grid, hipStream_t s);

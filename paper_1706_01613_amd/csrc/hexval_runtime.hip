@@ -337,9 +337,12 @@ static uint64_t pow2_ceil(uint64_t x)
 
 // ---------------------------------------------------------------- exact tier
 
-// Exact tier on host threads: the verdict of each element, or with
-// corner_only the corner-only test.
-static void run_exact_host(const double* pts, uint8_t* out, int64_t n, int max_depth, bool corner_only = false)
+// Exact tier on host threads.  pts: 24 doubles per element (hexahedra) or 8
+// (quadrangles).
+enum class ExactKind { kVerdict, kCornerTest, kQuad };
+
+static void run_exact_host(const double* pts, uint8_t* out, int64_t n, int max_depth,
+                           ExactKind kind = ExactKind::kVerdict)
 {
     if (n <= 0) return;
     const int64_t nt = std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()), 16);
@@ -350,7 +353,9 @@ static void run_exact_host(const double* pts, uint8_t* out, int64_t n, int max_d
         if (lo >= hi) break;
         th.emplace_back([=] {
             for (int64_t i = lo; i < hi; ++i)
-                out[i] = corner_only ? exact_corner_test(pts + 24 * i) : exact_verdict(pts + 24 * i, max_depth);
+                out[i] = kind == ExactKind::kQuad         ? exact_quad(pts + 8 * i)
+                         : kind == ExactKind::kCornerTest ? exact_corner_test(pts + 24 * i)
+                                                          : exact_verdict(pts + 24 * i, max_depth);
         });
     }
     for (auto& x : th) x.join();
@@ -826,10 +831,11 @@ int run_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts_in, do
     return HEXVAL_OK;
 }
 
-// Corner-only test and corner quality: one pass, then the exact tier for the
-// elements whose corner signs are not certified (in batches of the exact
-// list's capacity).
-int run_corner_test(const hexval_mesh_t* mesh, const hexval_opts_t* opts_in, uint8_t* test1, double* quality)
+// Corner-only test and corner quality, or linear quadrangles: one pass, then
+// the exact tier for the elements whose signs are not certified (in batches
+// of the exact list's capacity).
+static int run_corner_or_quad(const hexval_mesh_t* mesh, const hexval_opts_t* opts_in, uint8_t* test1,
+                              double* quality, bool quad)
 {
     hexval_opts_t o;
     if (opts_in) o = *opts_in;
@@ -867,7 +873,8 @@ int run_corner_test(const hexval_mesh_t* mesh, const hexval_opts_t* opts_in, uin
     const bool timing = st && st->timing;
     launch_reset(w.cnt, s);
     if (timing) HX_HIP(hipEventRecord(w.ev[0], s));
-    launch_corner_test(a, cus * 16, s);
+    if (quad) launch_quad_check(a, cus * 16, s);
+    else launch_corner_test(a, cus * 16, s);
     if (timing) HX_HIP(hipEventRecord(w.ev[1], s));
     HX_HIP(hipGetLastError());
     HX_HIP(hipMemcpyAsync(w.hcnt, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
@@ -875,11 +882,16 @@ int run_corner_test(const hexval_mesh_t* mesh, const hexval_opts_t* opts_in, uin
     uint64_t pending = w.hcnt->n_exact, settled = 0;
     while (pending > 0) {
         const int64_t k = (int64_t)std::min<uint64_t>(pending, w.exact_cap);
-        GatherArgs ga{a.q, a.mesh, nullptr, k, w.exact_pts};
-        launch_gather_exact(ga, s);
-        HX_HIP(hipMemcpyAsync(w.h_exact_pts, w.exact_pts, k * 24 * sizeof(double), hipMemcpyDeviceToHost, s));
+        const int per = quad ? 8 : 24;
+        if (quad) {
+            launch_quad_gather(a, k, w.exact_pts, s);
+        } else {
+            GatherArgs ga{a.q, a.mesh, nullptr, k, w.exact_pts};
+            launch_gather_exact(ga, s);
+        }
+        HX_HIP(hipMemcpyAsync(w.h_exact_pts, w.exact_pts, k * per * sizeof(double), hipMemcpyDeviceToHost, s));
         HX_HIP(hipStreamSynchronize(s));
-        run_exact_host(w.h_exact_pts, w.h_exact_v, k, 0, true);
+        run_exact_host(w.h_exact_pts, w.h_exact_v, k, 0, quad ? ExactKind::kQuad : ExactKind::kCornerTest);
         HX_HIP(hipMemcpyAsync(w.exact_v, w.h_exact_v, k, hipMemcpyHostToDevice, s));
         MeshDev sm = a.mesh;
         sm.min_coeff = nullptr;
@@ -906,6 +918,16 @@ int run_corner_test(const hexval_mesh_t* mesh, const hexval_opts_t* opts_in, uin
         }
     }
     return HEXVAL_OK;
+}
+
+int run_corner_test(const hexval_mesh_t* mesh, const hexval_opts_t* opts, uint8_t* test1, double* quality)
+{
+    return run_corner_or_quad(mesh, opts, test1, quality, false);
+}
+
+int run_quad_check(const hexval_mesh_t* mesh, const hexval_opts_t* opts, uint8_t* verdicts, double* min_j)
+{
+    return run_corner_or_quad(mesh, opts, verdicts, min_j, true);
 }
 
 int run_coefficients(const hexval_mesh_t* mesh, void* stream, double* coeffs)
@@ -951,6 +973,11 @@ int hexval_check(const double* points, const int32_t* connectivity, int64_t n, u
 int hexval_corner_test(const hexval_mesh_t* mesh, const hexval_opts_t* opts, uint8_t* test1, double* quality)
 {
     return run_corner_test(mesh, opts, test1, quality);
+}
+
+int hexval_quad_check(const hexval_mesh_t* mesh, const hexval_opts_t* opts, uint8_t* verdicts, double* min_j)
+{
+    return run_quad_check(mesh, opts, verdicts, min_j);
 }
 
 int hexval_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts, double rtol, double* lo, double* hi,

@@ -70,6 +70,9 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
 // Corner-only test and corner quality (hexval_corner_test).
 int run_corner_test(const hexval_mesh_t* mesh, const hexval_opts_t* opts, uint8_t* test1, double* quality);
 
+// Linear quadrangles (hexval_quad_check).
+int run_quad_check(const hexval_mesh_t* mesh, const hexval_opts_t* opts, uint8_t* verdicts, double* min_j);
+
 // Certified bounds of min J (hexval_min_jacobian).
 int run_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts, double rtol, double* lo, double* hi,
                      uint8_t* status);

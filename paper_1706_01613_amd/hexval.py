@@ -77,6 +77,8 @@ def lib():
             "hexval_check_batched": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t), I32,
                                                     ctypes.POINTER(hexval_opts_t), P, P]),
             "hexval_coefficients": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t), P, P]),
+            "hexval_quad_check": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t),
+                                                 ctypes.POINTER(hexval_opts_t), P, P]),
             "hexval_corner_test": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t),
                                                   ctypes.POINTER(hexval_opts_t), P, P]),
             "hexval_min_jacobian": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t),
@@ -187,6 +189,12 @@ def hexval_corner_test(mesh, opts, test1, quality=None):
                                            _addr(test1), _addr(quality)))
 
 
+def hexval_quad_check(mesh, opts, verdicts, min_j=None):
+    """C: hexval_quad_check."""
+    return _check(lib().hexval_quad_check(ctypes.byref(mesh), ctypes.byref(opts) if opts else None,
+                                          _addr(verdicts), _addr(min_j)))
+
+
 def hexval_min_jacobian(mesh, opts, rtol, lo, hi, status=None):
     """C: hexval_min_jacobian."""
     return _check(lib().hexval_min_jacobian(ctypes.byref(mesh), ctypes.byref(opts) if opts else None,
@@ -294,3 +302,22 @@ def corner_test(points, connectivity=None, validate_indices=False, stream=None, 
     opts = make_opts(FP64, 6, validate_indices, 0, 0, 0, stream, st)
     hexval_corner_test(make_mesh(points, connectivity, n), opts, test1, quality)
     return test1, quality, (st.as_dict() if stats else None)
+
+
+def quad_check(points, connectivity=None, validate_indices=False, stream=None, stats=False, want_min=True):
+    """Allocate outputs and run hexval_quad_check.  points: [n,4,2] float64, or
+    [m,2] with connectivity [n,4] int32.  Returns (verdicts, min_j or None,
+    stats dict or None)."""
+    import torch
+    n = connectivity.shape[0] if connectivity is not None else points.shape[0]
+    verdicts = torch.empty(n, dtype=torch.uint8, device=points.device)
+    min_j = torch.empty(n, dtype=torch.float64, device=points.device) if want_min else None
+    st = hexval_stats_t()
+    st.timing = 1 if stats else 0
+    if stream is None:
+        stream = torch.cuda.current_stream(points.device)
+    opts = make_opts(FP64, 6, validate_indices, 0, 0, 0, stream, st)
+    mesh = hexval_mesh_t(_addr(points), int(points.shape[0]) if connectivity is not None else 0,
+                         _addr(connectivity), int(n))
+    hexval_quad_check(mesh, opts, verdicts, min_j)
+    return verdicts, min_j, (st.as_dict() if stats else None)

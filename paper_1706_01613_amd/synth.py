@@ -150,6 +150,45 @@ def batched_meshes(n_meshes=10000, lo=2.0, hi=6.0, seed=4):
         yield V, conn
 
 
+# ---------------------------------------------------------------- quadrangles
+
+SQUARE = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], dtype=np.float64)
+
+
+def independent_quads(n, noise=0.4, seed=0):
+    """n independent quadrangles [n,4,2]: unit-square corners (order (0,0)
+    (1,0) (1,1) (0,1)) each displaced by U(-noise, noise)^2."""
+    rng = np.random.default_rng(seed)
+    return SQUARE[None] + rng.uniform(-noise, noise, size=(n, 4, 2))
+
+
+def quad_lattice(nx, ny, amp=0.2, wavelength=16.0, jitter_fraction=0.01, jitter=0.8, seed=0):
+    """A warped nx x ny quadrangle lattice: vertices [(nx+1)(ny+1), 2] float64
+    (vertex (i,j) -> id i + (nx+1) j, x = i + amp sin(2 pi j / wavelength),
+    y = j + amp sin(2 pi i / wavelength)), a fraction of them displaced by
+    U(-jitter, jitter)^2, and connectivity [nx ny, 4] int32 (quad (i,j) -> id
+    i + nx j, corners (i,j) (i+1,j) (i+1,j+1) (i,j+1))."""
+    w = 2.0 * math.pi / wavelength
+    i = np.arange(nx + 1, dtype=np.float64)
+    j = np.arange(ny + 1, dtype=np.float64)
+    V = np.empty((ny + 1, nx + 1, 2), dtype=np.float64)
+    V[..., 0] = i[None, :] + amp * np.sin(w * j)[:, None]
+    V[..., 1] = j[:, None] + amp * np.sin(w * i)[None, :]
+    V = V.reshape(-1, 2)
+    rng = np.random.default_rng(seed)
+    if jitter_fraction > 0:
+        sel = np.nonzero(rng.random(V.shape[0]) < jitter_fraction)[0]
+        V[sel] += rng.uniform(-jitter, jitter, size=(sel.size, 2))
+    sx = nx + 1
+    if (nx + 1) * (ny + 1) >= 2 ** 31:
+        raise ValueError("lattice too large for int32 vertex ids")
+    base = (np.arange(nx, dtype=np.int32)[None, :] + sx * np.arange(ny, dtype=np.int32)[:, None]).reshape(-1)
+    C = np.empty((base.size, 4), dtype=np.int32)
+    for k, off in enumerate((0, 1, 1 + sx, sx)):
+        C[:, k] = base + off
+    return V, C
+
+
 # ---------------------------------------------------------------- on device
 
 def warped_lattice_torch(nx, ny, nz, amp=0.2, wavelength=16.0, jitter=0.0, seed=0, device="cuda"):

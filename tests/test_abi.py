@@ -74,6 +74,8 @@ def test_argument_errors_without_gpu():
     o = hx.hexval_opts_default()
     o.precision = hx.FP32_FILTER
     assert L.hexval_min_jacobian(ctypes.byref(mesh), ctypes.byref(o), 1e-3, 32, 48, None) == hx.E_ARG
+    assert L.hexval_quad_check(None, None, 32, None) == hx.E_ARG
+    assert L.hexval_quad_check(ctypes.byref(mesh), None, None, None) == hx.E_ARG
     assert L.hexval_corner_test(None, None, 32, None) == hx.E_ARG
     assert L.hexval_corner_test(ctypes.byref(mesh), None, None, None) == hx.E_ARG
     empty = hx.hexval_mesh_t(None, 0, None, 0)

@@ -76,3 +76,18 @@ def test_config2_min_jacobian_every_element():
         ref = oracle.min_jacobian(V, C[a:b], rtol=1e-3, max_depth=6)
         assert ((lo[a:b] <= ref["hi"]) & (ref["lo"] <= hi[a:b])).all(), f"[{a}:{b}]"
         assert (ref["status"] == oracle.MJ_CONVERGED).all()
+
+
+def test_quad_lattice_8000_squared_every_element():
+    import oracle
+    torch = torch_cuda()
+    _say("quads: 8000^2 warped lattice, 1% of vertices jittered 0.8 (seed 0)")
+    V, C = synth.quad_lattice(8000, 8000, seed=0)
+    v, m, st = hx.quad_check(to_dev(torch, V), to_dev(torch, C), stats=True)
+    torch.cuda.synchronize()
+    v, m = v.cpu().numpy(), m.cpu().numpy()
+    _say(f"quad stats: {st}")
+    ref = oracle.quad_check(V, C)
+    assert np.array_equal(v, ref["verdict"])
+    assert np.abs(m - ref["min_j"]).max() <= 1e-13
+    assert 0 < np.count_nonzero(v == hx.INVALID) < v.size

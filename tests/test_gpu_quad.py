@@ -1,0 +1,78 @@
+"""GPU: linear quadrangle validity (Section 2.1) against the oracle: verdicts
+bit-exact, min J (the smallest corner value) to 1e-14 of S^2."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1706_01613_amd import hexval as hx
+from paper_1706_01613_amd import synth
+from tests._gpu import torch_cuda, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu(torch, P, conn=None, **kw):
+    v, m, st = hx.quad_check(to_dev(torch, P), None if conn is None else to_dev(torch, conn), stats=True, **kw)
+    torch.cuda.synchronize()
+    return v.cpu().numpy(), m.cpu().numpy(), st
+
+
+def _compare(v, m, P, conn=None, label=""):
+    ref = oracle.quad_check(P, conn)
+    bad = np.nonzero(v != ref["verdict"])[0]
+    assert bad.size == 0, f"{label}: {bad.size} verdict mismatches, first {bad[:8]}"
+    fin = np.isfinite(ref["min_j"])
+    assert np.array_equal(np.isfinite(m), fin), label
+    Q = P.reshape(-1, 4, 2) if conn is None else P.reshape(-1, 2)[conn]
+    S = np.abs(np.diff(Q[:, [0, 1, 2, 3, 0], :], axis=1)).max(axis=(1, 2))
+    err = np.abs(m[fin] - ref["min_j"][fin]) / np.maximum(S[fin] ** 2, 1e-300)
+    assert err.max(initial=0.0) <= 1e-14, label
+    return ref
+
+
+def test_quad_independent_against_oracle():
+    torch = torch_cuda()
+    P = synth.independent_quads(2_000_000, noise=0.4, seed=0)
+    v, m, st = _gpu(torch, P)
+    _say(f"stats {st}")
+    ref = _compare(v, m, P, label="independent")
+    assert 0 < np.count_nonzero(ref["verdict"] == oracle.INVALID) < P.shape[0]
+
+
+def test_quad_lattice_with_validation():
+    torch = torch_cuda()
+    V, C = synth.quad_lattice(1000, 700, seed=3)
+    C[5, 2] = -1
+    v, m, _ = _gpu(torch, V, C, validate_indices=True)
+    assert v[5] == hx.BAD_INPUT and np.isnan(m[5])
+    keep = np.ones(C.shape[0], bool)
+    keep[5] = False
+    _compare(v[keep], m[keep], V, C[keep], label="lattice")
+
+
+def test_quad_exact_tier_on_integer_quads():
+    torch = torch_cuda()
+    rng = np.random.default_rng(5)
+    P = (synth.SQUARE[None] * 2 + rng.integers(-1, 2, size=(300000, 4, 2))).astype(np.float64)
+    v, m, st = _gpu(torch, P)
+    assert st["n_exact"] > 0
+    _compare(v, m, P, label="integer")
+
+
+def test_quad_closed_forms_and_bad_input():
+    torch = torch_cuda()
+    sq = synth.SQUARE
+    A = np.array([[2.0, 0.5], [-0.3, 1.5]])
+    P = np.stack([sq, sq @ A.T + 3.0, sq[::-1], sq[[0, 1, 3, 2]],
+                  np.array([[0, 0], [2, 0], [0.5, 0.5], [0, 2]], dtype=np.float64), sq])
+    P[5, 0, 0] = np.nan
+    v, m, _ = _gpu(torch, P)
+    assert list(v) == [hx.VALID, hx.VALID, hx.INVALID, hx.INVALID, hx.INVALID, hx.BAD_INPUT]
+    assert m[0] == 1.0 and abs(m[1] - np.linalg.det(A)) < 1e-15 and np.isnan(m[5])
