@@ -44,7 +44,7 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # and the decisions.
 VALU_OPS_PER_HEX = 36 + 36 + 20 * 9 + 80 + 40
 KERNEL_SOURCES = ["hexval_kernels.hip", "hexval_kernels.hpp", "hexval_math.hpp", "hexval_internal.hpp"]
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_top_f64_range_lattice400_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_top_f64_conn_lattice400_traffic.md")
 
 
 def kernel_source_digest():
@@ -428,7 +428,7 @@ def main():
                    "inputs": "resident in HBM"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_top_f64_range (first pass)",
+                     "kernel": "k_top_f64_conn (first pass)",
                      "algorithmic_bytes_per_launch": alg,
                      "avg_launch_ms": float(first.mean()),
                      "valu": {"achieved": valu_ops, "peak": VALU_PEAK_OPS, "unit": "FP64 lane-ops/s",

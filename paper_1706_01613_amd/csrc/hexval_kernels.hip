@@ -217,50 +217,58 @@ __global__ __launch_bounds__(256) void k_roots(RootArgs a)
 // Tile scheduler of the first passes.  The tiles are cut into `xcds`
 // contiguous chunks; chunk x is served first to the blocks that the
 // dispatcher places on XCD x (block b runs on XCD b % xcds, 8 on MI355X), so
-// neighbouring tiles, which share vertices, meet in the same L2.  A block
-// takes runs of consecutive tiles from its chunk's counter (runs of up to 16
-// tiles, fewer when there are few tiles per block, so one atomic serves many
-// tiles), and once its chunk is used up takes runs from the other chunks, so
-// a chunk that costs more (private vertices, say) does not hold up the launch.
+// neighbouring tiles, which share vertices, meet in the same L2.  Work is
+// handed out in runs: with w blocks per chunk, run r of a chunk is the tiles
+// g*R*w + o + j*w (j < R, g = r / w, o = r % w, R up to 16), so the w blocks
+// working on a chunk sweep a window of about w consecutive tiles together
+// while one atomic serves R tiles.  A block whose chunk is used up takes
+// runs from the other chunks, so a chunk that costs more (private vertices,
+// say) does not hold up the launch.
 struct TileSched {
     int64_t n_tiles;
     int xcds, home;
-    int64_t run;                // tiles per grab
-    unsigned long long* next;   // Counters::tile_next
-    int64_t cur = 0, end = 0;   // the block's current run (block-uniform)
+    int64_t run;                // tiles per run (R)
+    int64_t width;              // blocks per chunk (w): stride of a run's tiles
+    unsigned long long* next;   // Counters::tile_next: runs taken per chunk
+    int64_t base = 0, j = 0, jend = 0;   // the block's current run (block-uniform)
     __device__ TileSched(int64_t n, int x, Counters* c)
         : n_tiles(n), xcds(x), home((int)(blockIdx.x % (unsigned)x)), next(c->tile_next)
     {
         const int64_t per_block = n / ((int64_t)gridDim.x * 4);
         run = per_block < 1 ? 1 : per_block > 16 ? 16 : per_block;
+        width = ((int64_t)gridDim.x + x - 1) / x;
     }
-    __device__ void grab(int64_t& lo, int64_t& hi)   // one thread of the block
+    // First tile of run r of a chunk of `size` tiles (>= size: no such run).
+    __device__ int64_t first_of(int64_t r) const { return (r / width) * run * width + r % width; }
+    __device__ void grab(int64_t& first, int64_t& count)   // one thread of the block
     {
         for (int k = 0; k < xcds; ++k) {
             const int c = (home + k) % xcds;
             const int64_t cs = n_tiles * c / xcds, size = n_tiles * (c + 1) / xcds - cs;
             unsigned long long* ctr = next + 32 * c;
-            if ((int64_t)load_relaxed(ctr) >= size) continue;   // used up: skip the atomic
-            const int64_t i = (int64_t)atomicAdd(ctr, (unsigned long long)run);
-            if (i < size) {
-                lo = cs + i;
-                hi = cs + (i + run < size ? i + run : size);
+            if (first_of((int64_t)load_relaxed(ctr)) >= size) continue;   // used up: skip the atomic
+            const int64_t f = first_of((int64_t)atomicAdd(ctr, 1ull));
+            if (f < size) {
+                const int64_t m = (size - f + width - 1) / width;
+                first = cs + f;
+                count = m < run ? m : run;
                 return;
             }
         }
-        lo = hi = 0;
+        first = count = 0;
     }
     // The block's next tile, or -1 when none is left (every thread calls it).
     __device__ int64_t next_tile()
     {
-        if (cur < end) return cur++;
+        if (j < jend) return base + (j++) * width;
         __shared__ int64_t range[2];
         __syncthreads();                 // everyone has read the previous run
         if (threadIdx.x == 0) grab(range[0], range[1]);
         __syncthreads();
-        cur = range[0];
-        end = range[1];
-        return cur < end ? cur++ : -1;
+        base = range[0];
+        jend = range[1];
+        j = 0;
+        return j < jend ? base + (j++) * width : -1;
     }
 };
 
