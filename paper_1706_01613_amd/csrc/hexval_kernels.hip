@@ -305,52 +305,77 @@ __device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F);
 // (s_waitcnt vmcnt(0)).
 __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-// Single mesh with trusted connectivity: as k_top_f64_range, but the connectivity of
-// a lane's next element is loaded together with the current element's
-// vertices, so each iteration waits for one round of memory latency, not two
-// dependent ones.  The prefetch goes straight to LDS (global_load_lds_dwordx4:
-// lane i of a wave lands at the wave's base + 16 i) and costs no registers.
-template <bool EDGES>
-__global__ __launch_bounds__(256) void k_top_f64_conn(TopArgs a)
+// First-pass loop over a single mesh with trusted connectivity (K corners per
+// element, 4 or 8): the connectivity row of a lane's next element is loaded
+// straight into LDS (global_load_lds_dwordx4: lane i of a wave lands at the
+// wave's base + 16 i, no registers) before the current element's vertex
+// loads, so both are in flight together and an iteration waits for one
+// round of memory latency instead of two dependent ones.  body(e, active,
+// idx) issues the vertex loads of idx (every lane holds a valid row: lanes
+// past the end hold row n-1), calls wait_vmem(), which also covers the
+// prefetch, and computes.  stage: [K/4][256] int4 in LDS.
+template <int K, typename Body>
+__device__ __forceinline__ void conn_prefetch_loop(const int32_t* conn, int64_t n, TileSched& ts, int4* stage,
+                                                   Body body)
 {
-    __shared__ int4 stage[2][256];   // corners 0-3 and 4-7 of each lane's next element
-    const MeshDev& m = a.mesh;
     const int wave_base = threadIdx.x & ~63;
-    TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
     auto prefetch = [&](int64_t t) {
         int64_t e = t * (int64_t)blockDim.x + threadIdx.x;
-        e = e < m.n ? e : m.n - 1;     // past the end: a valid row, ignored
-        const int* src = m.conn + 8 * e;
-        __builtin_amdgcn_global_load_lds(src, (lds_ptr)&stage[0][wave_base], 16, 0, 0);
-        __builtin_amdgcn_global_load_lds(src + 4, (lds_ptr)&stage[1][wave_base], 16, 0, 0);
+        e = e < n ? e : n - 1;        // past the end: a valid row, ignored
+        const int* src = conn + (int64_t)K * e;
+#pragma unroll
+        for (int h = 0; h < K / 4; ++h)
+            __builtin_amdgcn_global_load_lds(src + 4 * h, (lds_ptr)&stage[h * 256 + wave_base], 16, 0, 0);
     };
     int64_t t = ts.next_tile();
     if (t >= 0) prefetch(t);
     wait_vmem();
     while (t >= 0) {
         const int64_t e = t * (int64_t)blockDim.x + threadIdx.x;
-        const bool active = e < m.n;
         // this iteration's rows are in LDS: the wait after the previous
         // iteration's loads covered the prefetch issued before them
-        const int4 c0 = stage[0][threadIdx.x], c1 = stage[1][threadIdx.x];
-        const int idx[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-        // the next rows go out before this element's vertex loads, so both
-        // are in flight together (the last iteration reloads its own rows)
+        int idx[K];
+#pragma unroll
+        for (int h = 0; h < K / 4; ++h) {
+            const int4 c = stage[h * 256 + threadIdx.x];
+            idx[4 * h] = c.x;
+            idx[4 * h + 1] = c.y;
+            idx[4 * h + 2] = c.z;
+            idx[4 * h + 3] = c.w;
+        }
+        // the next rows go out before this element's vertex loads (the last
+        // iteration reloads its own rows)
         const int64_t tn = ts.next_tile();
         wait_lds();                    // the slots are free: every lane has read its row
         prefetch(tn >= 0 ? tn : t);
-        // trusted indices: every lane holds a valid row (lanes past the end
-        // hold row n-1), so the loads need no branch
-        V3 p[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const double* v = m.points + 3 * (int64_t)idx[k];
-            p[k] = {v[0], v[1], v[2]};
-        }
-        wait_vmem();                   // vertices and the next rows have landed
-        finish_element<EDGES>(m, 0, e, active, p, false, a.q, a.max_depth);
+        body(e, e < n, idx);
         t = tn;
     }
+}
+
+__device__ __forceinline__ void gather8(const double* points, const int idx[8], V3 p[8])
+{
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const double* v = points + 3 * (int64_t)idx[k];
+        p[k] = {v[0], v[1], v[2]};
+    }
+}
+
+// k_top_f64_range for a single mesh with trusted connectivity, through
+// conn_prefetch_loop.
+template <bool EDGES>
+__global__ __launch_bounds__(256) void k_top_f64_conn(TopArgs a)
+{
+    __shared__ int4 stage[2 * 256];
+    const MeshDev& m = a.mesh;
+    TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
+    conn_prefetch_loop<8>(m.conn, m.n, ts, stage, [&](int64_t e, bool active, const int* idx) {
+        V3 p[8];
+        gather8(m.points, idx, p);
+        wait_vmem();                   // vertices and the next rows have landed
+        finish_element<EDGES>(m, 0, e, active, p, false, a.q, a.max_depth);
+    });
 }
 
 template <bool BATCHED, bool EDGES>
@@ -377,15 +402,38 @@ __global__ __launch_bounds__(256) void k_top_f64_list(TopArgs a)
 // final here (min_coeff is the FP32 minimum, widened); every other element
 // is listed for the FP64 pass (k_top_f64_list), which decides it exactly as
 // the plain FP64 path would.
-template <int G>
-__device__ void filter_element(const MeshDev& m, int mesh_idx, int64_t e, bool active, const QueueDev& q)
+// Slot (in order of waves, then lanes) for each thread of the block with
+// `want`, from one atomic on *c per block.  Every thread of the block calls
+// it (it synchronizes the block).
+__device__ unsigned long long block_reserve(unsigned long long* c, bool want)
 {
-    V3 p[8];
-    bool bad = false;
+    __shared__ unsigned int wave_want[4];
+    __shared__ unsigned long long base;
+    const int wid = threadIdx.x >> 6;
+    const uint64_t mask = ballot(want);
+    if ((threadIdx.x & 63) == 0) wave_want[wid] = (unsigned int)__popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int total = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) total += wave_want[w];
+        base = total ? atomicAdd(c, (unsigned long long)total) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long off = base + (unsigned long long)lane_rank(mask);
+    for (int w = 0; w < wid; ++w) off += wave_want[w];
+    __syncthreads();   // wave_want and base are rewritten by the next call
+    return off;
+}
+
+// Every thread of the block calls this (block-level list reservation: one
+// atomic per block and tile instead of one per wave, which matters when
+// many elements need the FP64 pass).
+__device__ void filter_finish(const MeshDev& m, int mesh_idx, int64_t e, bool active, const V3 p[8], bool bad,
+                              const QueueDev& q)
+{
     int st = -1;
     float mn = 0.0f;
     if (active) {
-        load_points_t<G>(m, e, p, bad);
         if (!bad) {
             const LeanT<float> r = element_lean_t<float>(p, false);
             st = filter_state(r);
@@ -394,9 +442,8 @@ __device__ void filter_element(const MeshDev& m, int mesh_idx, int64_t e, bool a
     }
     const bool recheck = active && !bad && st < 0;
     uint8_t v = bad ? 3 : (uint8_t)st;
-    const uint64_t mask = ballot(recheck);
-    if (mask) {
-        const unsigned long long slot = wave_reserve(&q.cnt->n_list, mask);
+    if (__syncthreads_or(recheck)) {
+        const unsigned long long slot = block_reserve(&q.cnt->n_list, recheck);
         bool deferred = false;
         if (recheck) {
             if (slot < q.list_cap) {
@@ -414,6 +461,15 @@ __device__ void filter_element(const MeshDev& m, int mesh_idx, int64_t e, bool a
         m.verdict[e] = v;
         if (m.min_coeff && !recheck) m.min_coeff[e] = bad ? __builtin_nan("") : (double)mn;
     }
+}
+
+template <int G>
+__device__ void filter_element(const MeshDev& m, int mesh_idx, int64_t e, bool active, const QueueDev& q)
+{
+    V3 p[8];
+    bool bad = false;
+    if (active) load_points_t<G>(m, e, p, bad);
+    filter_finish(m, mesh_idx, e, active, p, bad, q);
 }
 
 template <bool BATCHED, int G>
@@ -435,6 +491,21 @@ __global__ __launch_bounds__(256) void k_filter_f32_range(TopArgs a)
         }
         filter_element<G>(m, mi, e, e < m.n, a.q);
     }
+}
+
+// k_filter_f32_range for a single mesh with trusted connectivity, through
+// conn_prefetch_loop.
+__global__ __launch_bounds__(256) void k_filter_f32_conn(TopArgs a)
+{
+    __shared__ int4 stage[2 * 256];
+    const MeshDev& m = a.mesh;
+    TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
+    conn_prefetch_loop<8>(m.conn, m.n, ts, stage, [&](int64_t e, bool active, const int* idx) {
+        V3 p[8];
+        gather8(m.points, idx, p);
+        wait_vmem();
+        filter_finish(m, 0, e, active, p, false, a.q);
+    });
 }
 
 // ------------------------------------------------------------ subdivision
@@ -696,63 +767,83 @@ constexpr int kMjConverged = 0, kMjCapped = 1, kMjQueueFull = 2, kMjBadInput = 3
 // first-pass arithmetic; elements whose bounds are not yet within tol are
 // listed for subdivision, up to root_cap of them, the rest deferred to the
 // next round.  Later rounds take their elements from in_list.
+__device__ void minj_element(const MinjArgs& a, int64_t e, bool active, const V3 p[8], bool bad)
+{
+    const QueueDev& q = a.q;
+    int st = -1;
+    double lo = 0.0, hi = 0.0, scale = 0.0;
+    if (active) {
+        if (bad) {
+            st = kMjBadInput;
+        } else {
+            const LeanResult r = element_lean(p, false);
+            if (!r.certified_range) {
+                bool finite = true;
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    finite = finite && isfinite(p[k].x) && isfinite(p[k].y) && isfinite(p[k].z);
+                st = finite ? kMjOutOfRange : kMjBadInput;
+            } else {
+                lo = r.min27;
+                hi = r.m20;
+                scale = r.scale;
+                const double tol = a.mj.rtol * scale / 6.0;
+                if (lo >= hi - tol) st = kMjConverged;
+                else if (a.max_depth == 0) st = kMjCapped;
+            }
+        }
+    }
+    const bool push = active && st < 0;
+    const uint64_t pmask = ballot(push);
+    bool defer = false;
+    if (pmask) {
+        const unsigned long long slot = wave_reserve(&q.cnt->n_sub, pmask);
+        if (push) {
+            if (slot < a.root_cap) {
+                q.sub_elem[slot] = e;
+                q.sub_mesh[slot] = 0;
+            } else {
+                defer = true;
+            }
+        }
+    }
+    const uint64_t dmask = ballot(defer);
+    if (dmask) {
+        const unsigned long long d = wave_reserve(&q.cnt->n_deferred, dmask);
+        if (defer) a.out_list[d] = e;
+    }
+    if (active && st >= 0) minj_write(a, e, lo, hi, scale, st);
+}
+
 __global__ __launch_bounds__(256) void k_minj_top(MinjArgs a)
 {
     const MeshDev& m = a.mesh;
-    const QueueDev& q = a.q;
     const int64_t count = a.in_list ? a.in_count : m.n;
-    TileSched ts(a.n_tiles, a.xcds, q.cnt);
+    TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
     for (int64_t t = ts.next_tile(); t >= 0; t = ts.next_tile()) {
         const int64_t i = t * (int64_t)blockDim.x + threadIdx.x;
         const bool active = i < count;
         const int64_t e = !active ? 0 : a.in_list ? a.in_list[i] : i;
-        int st = -1;
-        double lo = 0.0, hi = 0.0, scale = 0.0;
-        if (active) {
-            V3 p[8];
-            bool bad = false;
-            load_points(m, e, p, bad);
-            if (bad) {
-                st = kMjBadInput;
-            } else {
-                const LeanResult r = element_lean(p, false);
-                if (!r.certified_range) {
-                    bool finite = true;
-#pragma unroll
-                    for (int k = 0; k < 8; ++k)
-                        finite = finite && isfinite(p[k].x) && isfinite(p[k].y) && isfinite(p[k].z);
-                    st = finite ? kMjOutOfRange : kMjBadInput;
-                } else {
-                    lo = r.min27;
-                    hi = r.m20;
-                    scale = r.scale;
-                    const double tol = a.mj.rtol * scale / 6.0;
-                    if (lo >= hi - tol) st = kMjConverged;
-                    else if (a.max_depth == 0) st = kMjCapped;
-                }
-            }
-        }
-        const bool push = active && st < 0;
-        const uint64_t pmask = ballot(push);
-        bool defer = false;
-        if (pmask) {
-            const unsigned long long slot = wave_reserve(&q.cnt->n_sub, pmask);
-            if (push) {
-                if (slot < a.root_cap) {
-                    q.sub_elem[slot] = e;
-                    q.sub_mesh[slot] = 0;
-                } else {
-                    defer = true;
-                }
-            }
-        }
-        const uint64_t dmask = ballot(defer);
-        if (dmask) {
-            const unsigned long long d = wave_reserve(&q.cnt->n_deferred, dmask);
-            if (defer) a.out_list[d] = e;
-        }
-        if (active && st >= 0) minj_write(a, e, lo, hi, scale, st);
+        V3 p[8];
+        bool bad = false;
+        if (active) load_points(m, e, p, bad);
+        minj_element(a, e, active, p, bad);
     }
+}
+
+// k_minj_top over a whole single mesh with trusted connectivity (the first
+// round), through conn_prefetch_loop.
+__global__ __launch_bounds__(256) void k_minj_top_conn(MinjArgs a)
+{
+    __shared__ int4 stage[2 * 256];
+    const MeshDev& m = a.mesh;
+    TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
+    conn_prefetch_loop<8>(m.conn, m.n, ts, stage, [&](int64_t e, bool active, const int* idx) {
+        V3 p[8];
+        gather8(m.points, idx, p);
+        wait_vmem();
+        minj_element(a, e, active, p, false);
+    });
 }
 
 // Root boxes of the listed elements: full coefficients, their minimum (word
@@ -1089,60 +1180,65 @@ __device__ __forceinline__ double cross2(double ax, double ay, double bx, double
     return fma(ax, by, -(ay * bx));
 }
 
-__global__ __launch_bounds__(256) void k_quad_check(CornerArgs a)
+__device__ __forceinline__ void quad_element(const CornerArgs& a, int64_t e, bool active, const double2 p[4], bool bad)
 {
     const MeshDev& m = a.mesh;
     const QueueDev& q = a.q;
-    TileSched ts(a.n_tiles, a.xcds, q.cnt);
+    uint8_t v = 0;
+    double mn = __builtin_nan("");
+    bool exact = false;
+    if (active) {
+        bool finite = !bad;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) finite = finite && isfinite(p[k].x) && isfinite(p[k].y);
+        if (!finite) {
+            v = 3;
+        } else {
+            // x_xi on eta = 0 and 1, x_eta on xi = 0 and 1
+            const double ax0 = p[1].x - p[0].x, ay0 = p[1].y - p[0].y;
+            const double ax1 = p[2].x - p[3].x, ay1 = p[2].y - p[3].y;
+            const double bx0 = p[3].x - p[0].x, by0 = p[3].y - p[0].y;
+            const double bx1 = p[2].x - p[1].x, by1 = p[2].y - p[1].y;
+            const double S = fmax(fmax(fmax(fabs(ax0), fabs(ay0)), fmax(fabs(ax1), fabs(ay1))),
+                                  fmax(fmax(fabs(bx0), fabs(by0)), fmax(fabs(bx1), fabs(by1))));
+            const double J0 = cross2(ax0, ay0, bx0, by0);   // (0,0)
+            const double J1 = cross2(ax0, ay0, bx1, by1);   // (1,0)
+            const double J2 = cross2(ax1, ay1, bx1, by1);   // (1,1)
+            const double J3 = cross2(ax1, ay1, bx0, by0);   // (0,1)
+            mn = fmin(fmin(J0, J1), fmin(J2, J3));
+            const double tau = 9.0 * kU64 * S * S;
+            const bool in_range = S >= 0x1p-450 && S <= 0x1p+450;
+            if (!in_range) exact = true;
+            else if (mn <= -tau) v = 0;
+            else if (mn > tau) v = 1;
+            else exact = true;
+        }
+    }
+    const uint64_t xmask = ballot(exact);
+    if (xmask) {
+        const unsigned long long slot = wave_reserve(&q.cnt->n_exact, xmask);
+        if (exact && slot < q.exact_cap) {
+            q.exact_elem[slot] = e;
+            q.exact_mesh[slot] = 0;
+        }
+    }
+    if (exact) v = kExact;
+    if (active) {
+        m.verdict[e] = v;
+        if (a.quality) a.quality[e] = mn;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_quad_check(CornerArgs a)
+{
+    TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
     for (int64_t t = ts.next_tile(); t >= 0; t = ts.next_tile()) {
         const int64_t e = t * (int64_t)blockDim.x + threadIdx.x;
-        const bool active = e < m.n;
-        uint8_t v = 0;
-        double mn = __builtin_nan("");
-        bool exact = false;
-        if (active) {
-            double2 p[4];
-            bool bad = false;
-            load_quad(m, e, p, bad);
-            bool finite = !bad;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) finite = finite && isfinite(p[k].x) && isfinite(p[k].y);
-            if (!finite) {
-                v = 3;
-            } else {
-                // x_xi on eta = 0 and 1, x_eta on xi = 0 and 1
-                const double ax0 = p[1].x - p[0].x, ay0 = p[1].y - p[0].y;
-                const double ax1 = p[2].x - p[3].x, ay1 = p[2].y - p[3].y;
-                const double bx0 = p[3].x - p[0].x, by0 = p[3].y - p[0].y;
-                const double bx1 = p[2].x - p[1].x, by1 = p[2].y - p[1].y;
-                const double S = fmax(fmax(fmax(fabs(ax0), fabs(ay0)), fmax(fabs(ax1), fabs(ay1))),
-                                      fmax(fmax(fabs(bx0), fabs(by0)), fmax(fabs(bx1), fabs(by1))));
-                const double J0 = cross2(ax0, ay0, bx0, by0);   // (0,0)
-                const double J1 = cross2(ax0, ay0, bx1, by1);   // (1,0)
-                const double J2 = cross2(ax1, ay1, bx1, by1);   // (1,1)
-                const double J3 = cross2(ax1, ay1, bx0, by0);   // (0,1)
-                mn = fmin(fmin(J0, J1), fmin(J2, J3));
-                const double tau = 9.0 * kU64 * S * S;
-                const bool in_range = S >= 0x1p-450 && S <= 0x1p+450;
-                if (!in_range) exact = true;
-                else if (mn <= -tau) v = 0;
-                else if (mn > tau) v = 1;
-                else exact = true;
-            }
-        }
-        const uint64_t xmask = ballot(exact);
-        if (xmask) {
-            const unsigned long long slot = wave_reserve(&q.cnt->n_exact, xmask);
-            if (exact && slot < q.exact_cap) {
-                q.exact_elem[slot] = e;
-                q.exact_mesh[slot] = 0;
-            }
-        }
-        if (exact) v = kExact;
-        if (active) {
-            m.verdict[e] = v;
-            if (a.quality) a.quality[e] = mn;
-        }
+        const bool active = e < a.mesh.n;
+        double2 p[4];
+        bool bad = false;
+        if (active) load_quad(a.mesh, e, p, bad);
+        quad_element(a, e, active, p, bad);
     }
 }
 
@@ -1281,7 +1377,7 @@ void launch_filter_range(const TopArgs& a, bool batched, int grid, int block, hi
     }
     if (!a.mesh.conn) HX_LAUNCH((k_filter_f32_range<false, kGatherPoints>), grid, block, s, a);
     else if (a.mesh.validate) HX_LAUNCH((k_filter_f32_range<false, kGatherChecked>), grid, block, s, a);
-    else HX_LAUNCH((k_filter_f32_range<false, kGatherConn>), grid, block, s, a);
+    else HX_LAUNCH(k_filter_f32_conn, grid, block, s, a);
 }
 
 void launch_top_list(const TopArgs& a, bool batched, int grid, int block, hipStream_t s)
@@ -1317,13 +1413,19 @@ void launch_scatter_exact(const ScatterArgs& a, hipStream_t s)
 }
 void launch_corner_test(const CornerArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_corner_test, grid, 256, s, a); }
 void launch_corner_collect(const CornerArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_corner_collect, grid, 256, s, a); }
+// (The quadrangle kernel needs about 50 registers, so occupancy already
+// hides its gather latency; the prefetching loop measured slower for it.)
 void launch_quad_check(const CornerArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_quad_check, grid, 256, s, a); }
 void launch_quad_gather(const CornerArgs& a, int64_t n, double* out, hipStream_t s)
 {
     const int64_t g = (n + 255) / 256;
     HX_LAUNCH(k_quad_gather, g < 4096 ? g : 4096, 256, s, a, n, out);
 }
-void launch_minj_top(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_top, grid, 256, s, a); }
+void launch_minj_top(const MinjArgs& a, int grid, hipStream_t s)
+{
+    if (!a.in_list && a.mesh.conn && !a.mesh.validate) HX_LAUNCH(k_minj_top_conn, grid, 256, s, a);
+    else HX_LAUNCH(k_minj_top, grid, 256, s, a);
+}
 void launch_minj_roots(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_roots, grid, 256, s, a); }
 void launch_minj_level(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_level, grid, 256, s, a); }
 void launch_minj_fold(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_fold, grid, 256, s, a); }

@@ -873,8 +873,9 @@ static int run_corner_or_quad(const hexval_mesh_t* mesh, const hexval_opts_t* op
     const bool timing = st && st->timing;
     launch_reset(w.cnt, s);
     if (timing) HX_HIP(hipEventRecord(w.ev[0], s));
-    if (quad) launch_quad_check(a, cus * 16, s);
-    else launch_corner_test(a, cus * 16, s);
+    const int grid = o.grid_blocks ? (int)std::max<int64_t>(8, (o.grid_blocks + 7) / 8 * 8) : cus * 8;
+    if (quad) launch_quad_check(a, grid, s);
+    else launch_corner_test(a, grid, s);
     if (timing) HX_HIP(hipEventRecord(w.ev[1], s));
     HX_HIP(hipGetLastError());
     HX_HIP(hipMemcpyAsync(w.hcnt, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));

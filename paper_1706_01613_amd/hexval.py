@@ -304,7 +304,8 @@ def corner_test(points, connectivity=None, validate_indices=False, stream=None, 
     return test1, quality, (st.as_dict() if stats else None)
 
 
-def quad_check(points, connectivity=None, validate_indices=False, stream=None, stats=False, want_min=True):
+def quad_check(points, connectivity=None, validate_indices=False, stream=None, stats=False, want_min=True,
+               grid_blocks=0):
     """Allocate outputs and run hexval_quad_check.  points: [n,4,2] float64, or
     [m,2] with connectivity [n,4] int32.  Returns (verdicts, min_j or None,
     stats dict or None)."""
@@ -316,7 +317,7 @@ def quad_check(points, connectivity=None, validate_indices=False, stream=None, s
     st.timing = 1 if stats else 0
     if stream is None:
         stream = torch.cuda.current_stream(points.device)
-    opts = make_opts(FP64, 6, validate_indices, 0, 0, 0, stream, st)
+    opts = make_opts(FP64, 6, validate_indices, 0, 0, grid_blocks, stream, st)
     mesh = hexval_mesh_t(_addr(points), int(points.shape[0]) if connectivity is not None else 0,
                          _addr(connectivity), int(n))
     hexval_quad_check(mesh, opts, verdicts, min_j)
