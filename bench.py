@@ -350,6 +350,34 @@ def quad_leg(hx, torch, synth, steps, n=8000):
             "invalid": int((v == hx.INVALID).sum()), "stats": st.as_dict()}
 
 
+def exact_tier_leg(hx, torch, synth, n=1_000_000):
+    """The exact tier: n integer hexes (2 x unit cube + U{-1,0,1}^3 per
+    coordinate, seed 12, every fourth with two coincident corners), most of
+    whose values and coefficients are exactly 0 or too close to 0 for the
+    FP64 bounds.  Once as they are (integers: the device tier settles what
+    needs no subdivision) and once with one coordinate per element moved to
+    2^-60 (a span beyond the device tier's integers: everything uncertain
+    goes to the host)."""
+    rng = np.random.default_rng(12)
+    P = (synth.CUBE[None] * 2 + rng.integers(-1, 2, size=(n, 8, 3))).astype(np.float64)
+    P[::4, 1] = P[::4, 0]
+    W = P.copy()
+    W[:, 0, 2] = np.where(W[:, 0, 2] == 0.0, 2.0 ** -60, W[:, 0, 2])
+    out = {"workload": f"{n} integer hexes with exact zeros (device tier) / with a 2^-60 coordinate "
+                       "(host tier)"}
+    for name, X in (("device", P), ("host", W)):
+        Xd = torch.from_numpy(X).to("cuda")
+        hx.check(Xd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, st = hx.check(Xd, stats=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[name] = {"ms": 1e3 * wall, "n_exact": st["n_exact"], "n_exact_host": st["n_exact_host"],
+                     "exact_elements_per_s": st["n_exact"] / wall}
+    return out
+
+
 def copy_calibration(torch, nbytes=1 << 30):
     """A plain device copy of known size, for scaling the profiler's
     FETCH_SIZE / WRITE_SIZE counters."""
@@ -456,6 +484,9 @@ def main():
         out["corner_test_vs_full"] = corner_test_leg(hx, torch, synth, 5)
         log(f"corner leg {out['corner_test_vs_full']}")
         torch.cuda.empty_cache()
+        log("exact tier leg")
+        out["exact_tier"] = exact_tier_leg(hx, torch, synth)
+        log(f"exact tier leg {out['exact_tier']}")
         log("batched leg")
         out["batched"] = batched_leg(hx, torch, synth, 3)
         log(f"batched leg {out['batched']}")

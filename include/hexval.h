@@ -90,7 +90,7 @@ typedef struct {
     int64_t n_elements;    /* elements checked */
     int64_t n_subdivided;  /* elements sent to subdivision */
     int64_t n_nodes;       /* sub-boxes evaluated by the subdivision kernel */
-    int64_t n_exact;       /* elements settled by the exact tier */
+    int64_t n_exact;       /* elements settled by the exact tier (device, else host) */
     int64_t n_recheck;     /* FP32_FILTER: elements recomputed in FP64 */
     int64_t n_rounds;      /* passes (more than 1 only after queue overflow) */
     int32_t max_level;     /* deepest sub-box level evaluated */
@@ -100,7 +100,9 @@ typedef struct {
     float ms_subdivision;  /* device time of subdivision drain + verdict fold */
     float ms_total;        /* device time from first launch to last kernel */
     int32_t block_threads; /* first-pass block size used (tuned or given) */
-    int32_t reserved;
+    int32_t n_exact_host;  /* of n_exact: elements the device exact tier left to
+                              the host (exact subdivision or a coordinate span
+                              over 78 bits) */
     int64_t grid_blocks;   /* first-pass grid used */
 } hexval_stats_t;
 

@@ -16,6 +16,7 @@
 //                  collection, exact-tier gather/scatter, coefficients.
 #include <hip/hip_runtime.h>
 
+#include "hexval_exact_dev.hpp"
 #include "hexval_internal.hpp"
 #include "hexval_kernels.hpp"
 #include "hexval_math.hpp"
@@ -1258,6 +1259,15 @@ __global__ void k_quad_gather(CornerArgs a, int64_t n, double* out)
     }
 }
 
+// mode 0: verdict (points: 24 doubles per entry), 1: corner-only test (24),
+// 2: quadrangle (8).
+__global__ __launch_bounds__(64) void k_exact_device(const double* pts, uint8_t* out, int64_t n, int mode,
+                                                     int max_depth)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = mode == 2 ? exact_device_quad(pts + 8 * i) : exact_device_hex(pts + 24 * i, max_depth, mode == 1);
+}
+
 // ------------------------------------------------------------ small kernels
 
 __global__ void k_reset(Counters* c)
@@ -1429,6 +1439,12 @@ void launch_minj_top(const MinjArgs& a, int grid, hipStream_t s)
 void launch_minj_roots(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_roots, grid, 256, s, a); }
 void launch_minj_level(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_level, grid, 256, s, a); }
 void launch_minj_fold(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_fold, grid, 256, s, a); }
+
+void launch_exact_device(const double* pts, uint8_t* out, int64_t n, int mode, int max_depth, hipStream_t s)
+{
+    const int64_t g = (n + 63) / 64;
+    HX_LAUNCH(k_exact_device, g < 1024 ? g : 1024, 64, s, pts, out, n, mode, max_depth);
+}
 
 void launch_coefficients(const MeshDev& m, double* out, hipStream_t s)
 {

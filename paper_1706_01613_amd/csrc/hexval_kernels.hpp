@@ -119,5 +119,8 @@ void launch_collect_deferred(const CollectArgs& a, int grid, hipStream_t s);
 void launch_gather_exact(const GatherArgs& a, hipStream_t s);
 void launch_scatter_exact(const ScatterArgs& a, hipStream_t s);
 void launch_coefficients(const MeshDev& m, double* out, hipStream_t s);
+// Device exact tier over gathered points (mode 0 verdict, 1 corner-only test,
+// 2 quadrangle); out[i] = result, or 0xFE where the host tier must decide.
+void launch_exact_device(const double* pts, uint8_t* out, int64_t n, int mode, int max_depth, hipStream_t s);
 
 }  // namespace hexval

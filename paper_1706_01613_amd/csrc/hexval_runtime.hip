@@ -337,28 +337,48 @@ static uint64_t pow2_ceil(uint64_t x)
 
 // ---------------------------------------------------------------- exact tier
 
-// Exact tier on host threads.  pts: 24 doubles per element (hexahedra) or 8
+// Kinds of exact decisions: pts hold 24 doubles per element (hexahedra) or 8
 // (quadrangles).
 enum class ExactKind { kVerdict, kCornerTest, kQuad };
 
-static void run_exact_host(const double* pts, uint8_t* out, int64_t n, int max_depth,
-                           ExactKind kind = ExactKind::kVerdict)
+// Device exact tier over the n gathered elements in `pts` (device), then the
+// host tier for those it leaves (0xFE); results in `v` (device) and `hv`
+// (host).  Returns the number settled on the host.
+static int exact_tier(Workspace& w, const double* pts, uint8_t* v, uint8_t* hv, double* hpts, int64_t n,
+                      int per, ExactKind kind, int max_depth, hipStream_t s, int64_t* host_count)
 {
-    if (n <= 0) return;
+    launch_exact_device(pts, v, n, kind == ExactKind::kQuad ? 2 : kind == ExactKind::kCornerTest ? 1 : 0,
+                        max_depth, s);
+    HX_HIP(hipGetLastError());
+    HX_HIP(hipMemcpyAsync(hv, v, n, hipMemcpyDeviceToHost, s));
+    HX_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> left;
+    for (int64_t i = 0; i < n; ++i)
+        if (hv[i] == 0xFE) left.push_back(i);
+    *host_count = (int64_t)left.size();
+    if (left.empty()) return HEXVAL_OK;
+    HX_HIP(hipMemcpyAsync(hpts, pts, n * per * sizeof(double), hipMemcpyDeviceToHost, s));
+    HX_HIP(hipStreamSynchronize(s));
+    const int64_t m = (int64_t)left.size();
     const int64_t nt = std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()), 16);
-    const int64_t per = (n + nt - 1) / nt;
+    const int64_t chunk = (m + nt - 1) / nt;
     std::vector<std::thread> th;
     for (int64_t t = 0; t < nt; ++t) {
-        const int64_t lo = t * per, hi = std::min(n, lo + per);
+        const int64_t lo = t * chunk, hi = std::min(m, lo + chunk);
         if (lo >= hi) break;
-        th.emplace_back([=] {
-            for (int64_t i = lo; i < hi; ++i)
-                out[i] = kind == ExactKind::kQuad         ? exact_quad(pts + 8 * i)
-                         : kind == ExactKind::kCornerTest ? exact_corner_test(pts + 24 * i)
-                                                          : exact_verdict(pts + 24 * i, max_depth);
+        th.emplace_back([&, lo, hi] {
+            for (int64_t k = lo; k < hi; ++k) {
+                const int64_t i = left[k];
+                hv[i] = kind == ExactKind::kQuad         ? exact_quad(hpts + 8 * i)
+                        : kind == ExactKind::kCornerTest ? exact_corner_test(hpts + 24 * i)
+                                                         : exact_verdict(hpts + 24 * i, max_depth);
+            }
         });
     }
     for (auto& x : th) x.join();
+    HX_HIP(hipMemcpyAsync(v, hv, n, hipMemcpyHostToDevice, s));
+    (void)w;
+    return HEXVAL_OK;
 }
 
 // ---------------------------------------------------------------- autotuner
@@ -667,10 +687,11 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         if (n_ex > 0) {
             GatherArgs ga{q, single, dmeshes, n_ex, w.exact_pts};
             launch_gather_exact(ga, s);
-            HX_HIP(hipMemcpyAsync(w.h_exact_pts, w.exact_pts, n_ex * 24 * sizeof(double), hipMemcpyDeviceToHost, s));
-            HX_HIP(hipStreamSynchronize(s));
-            run_exact_host(w.h_exact_pts, w.h_exact_v, n_ex, o.max_depth);
-            HX_HIP(hipMemcpyAsync(w.exact_v, w.h_exact_v, n_ex, hipMemcpyHostToDevice, s));
+            int64_t on_host = 0;
+            if ((rc = exact_tier(w, w.exact_pts, w.exact_v, w.h_exact_v, w.h_exact_pts, n_ex, 24,
+                                 ExactKind::kVerdict, o.max_depth, s, &on_host)))
+                return rc;
+            if (st) st->n_exact_host += (int32_t)on_host;
             ScatterArgs sa{q, single, dmeshes, n_ex, w.exact_v};
             launch_scatter_exact(sa, s);
             HX_HIP(hipGetLastError());
@@ -881,19 +902,20 @@ static int run_corner_or_quad(const hexval_mesh_t* mesh, const hexval_opts_t* op
     HX_HIP(hipMemcpyAsync(w.hcnt, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
     HX_HIP(hipStreamSynchronize(s));
     uint64_t pending = w.hcnt->n_exact, settled = 0;
+    int64_t on_host = 0;
     while (pending > 0) {
         const int64_t k = (int64_t)std::min<uint64_t>(pending, w.exact_cap);
-        const int per = quad ? 8 : 24;
         if (quad) {
             launch_quad_gather(a, k, w.exact_pts, s);
         } else {
             GatherArgs ga{a.q, a.mesh, nullptr, k, w.exact_pts};
             launch_gather_exact(ga, s);
         }
-        HX_HIP(hipMemcpyAsync(w.h_exact_pts, w.exact_pts, k * per * sizeof(double), hipMemcpyDeviceToHost, s));
-        HX_HIP(hipStreamSynchronize(s));
-        run_exact_host(w.h_exact_pts, w.h_exact_v, k, 0, quad ? ExactKind::kQuad : ExactKind::kCornerTest);
-        HX_HIP(hipMemcpyAsync(w.exact_v, w.h_exact_v, k, hipMemcpyHostToDevice, s));
+        int64_t on_host_k = 0;
+        if ((rc = exact_tier(w, w.exact_pts, w.exact_v, w.h_exact_v, w.h_exact_pts, k, quad ? 8 : 24,
+                             quad ? ExactKind::kQuad : ExactKind::kCornerTest, 0, s, &on_host_k)))
+            return rc;
+        on_host += on_host_k;
         MeshDev sm = a.mesh;
         sm.min_coeff = nullptr;
         ScatterArgs sa{a.q, sm, nullptr, k, w.exact_v};
@@ -912,6 +934,7 @@ static int run_corner_or_quad(const hexval_mesh_t* mesh, const hexval_opts_t* op
     if (st) {
         st->n_elements = n;
         st->n_exact = (int64_t)settled;
+        st->n_exact_host = (int32_t)on_host;
         st->n_rounds = 1;
         if (timing) {
             hipEventElapsedTime(&st->ms_first_pass, w.ev[0], w.ev[1]);

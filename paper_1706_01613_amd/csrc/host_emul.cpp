@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "hexval_exact.hpp"
+#include "hexval_exact_dev.hpp"
 #include "hexval_math.hpp"
 
 using namespace hexval;
@@ -167,6 +168,23 @@ void hexval_emul_check(const double* pts, const int32_t* conn, int64_t n, int ma
 }
 
 // The library's exact tier on n elements [n,8,3].
+// The device exact tier on the host: mode 0 verdict (24 doubles per
+// element), 1 corner-only test (24), 2 quadrangle (8); 0xFE = left to the
+// host tier.
+void hexval_emul_exact_device(const double* pts, int64_t n, int mode, int max_depth, uint8_t* out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = mode == 2 ? exact_device_quad(pts + 8 * i) : exact_device_hex(pts + 24 * i, max_depth, mode == 1);
+}
+
+// The host exact tier: mode 0 verdict, 1 corner-only test, 2 quadrangle.
+void hexval_emul_exact_host(const double* pts, int64_t n, int mode, int max_depth, uint8_t* out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = mode == 2 ? exact_quad(pts + 8 * i) : mode == 1 ? exact_corner_test(pts + 24 * i)
+                                                                 : exact_verdict(pts + 24 * i, max_depth);
+}
+
 void hexval_emul_exact(const double* pts, int64_t n, int max_depth, uint8_t* verdicts)
 {
     for (int64_t e = 0; e < n; ++e) verdicts[e] = exact_verdict(pts + 24 * e, max_depth);

@@ -37,7 +37,7 @@ class hexval_stats_t(ctypes.Structure):
                 ("max_level", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("ms_first_pass", ctypes.c_float), ("ms_recheck", ctypes.c_float),
                 ("ms_subdivision", ctypes.c_float), ("ms_total", ctypes.c_float),
-                ("block_threads", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("block_threads", ctypes.c_int32), ("n_exact_host", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int64)]
 
     def as_dict(self):

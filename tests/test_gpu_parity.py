@@ -122,7 +122,27 @@ def test_exact_tier_integer_lattice():
     P[:50, 3] = P[:50, 0]
     v, m, st = _run(torch, P)
     assert st["n_exact"] > 0
+    # the device tier settles step-2/step-4 decisions; only elements that need
+    # exact subdivision reach the host
+    assert st["n_exact_host"] < st["n_exact"]
     assert_parity(v, m, P, label="integer lattice")
+
+
+def test_exact_tier_device_and_host_split():
+    # the same integer hexes scaled so that one coordinate has a tiny
+    # exponent: the span exceeds the device tier's 78 bits and every uncertain
+    # element goes to the host; results are the same either way
+    torch = torch_cuda()
+    rng = np.random.default_rng(2)
+    P = (CUBE[None] * 2 + rng.integers(-1, 2, size=(3000, 8, 3))).astype(np.float64)
+    v, m, st = _run(torch, P)
+    W = P.copy()
+    W[:, 0, 2] = np.where(W[:, 0, 2] == 0.0, 2.0 ** -60, W[:, 0, 2])
+    vw, mw, stw = _run(torch, W)
+    _say(f"device/host split: {st['n_exact']}/{st['n_exact_host']} vs {stw['n_exact']}/{stw['n_exact_host']}")
+    assert st["n_exact_host"] < st["n_exact"]
+    assert_parity(v, m, P, label="integer")
+    assert_parity(vw, mw, W, label="wide span")
 
 
 def test_bad_input_and_index_validation():
