@@ -215,10 +215,15 @@ __global__ __launch_bounds__(256) void k_roots(RootArgs a)
     }
 }
 
+// XCD (accelerator complex die) the calling wave runs on: bits 3:0 of the
+// XCC_ID hardware register (0..7 on MI355X).
+__device__ __forceinline__ int xcd_id() { return (int)(__builtin_amdgcn_s_getreg(20 | (3 << 11)) & 15); }
+
 // Tile scheduler of the first passes.  The tiles are cut into `xcds`
-// contiguous chunks; chunk x is served first to the blocks that the
-// dispatcher places on XCD x (block b runs on XCD b % xcds, 8 on MI355X), so
-// neighbouring tiles, which share vertices, meet in the same L2.  Work is
+// contiguous chunks; chunk x is served first to the blocks that run on XCD x
+// (read from the hardware, which also holds when other kernels share the
+// device and the dispatcher's placement no longer follows the block index),
+// so neighbouring tiles, which share vertices, meet in the same L2.  Work is
 // handed out in runs: with w blocks per chunk, run r of a chunk is the tiles
 // g*R*w + o + j*w (j < R, g = r / w, o = r % w, R up to 16), so the w blocks
 // working on a chunk sweep a window of about w consecutive tiles together
@@ -233,7 +238,7 @@ struct TileSched {
     unsigned long long* next;   // Counters::tile_next: runs taken per chunk
     int64_t base = 0, j = 0, jend = 0;   // the block's current run (block-uniform)
     __device__ TileSched(int64_t n, int x, Counters* c)
-        : n_tiles(n), xcds(x), home((int)(blockIdx.x % (unsigned)x)), next(c->tile_next)
+        : n_tiles(n), xcds(x), home(xcd_id() % x), next(c->tile_next)
     {
         const int64_t per_block = n / ((int64_t)gridDim.x * 4);
         run = per_block < 1 ? 1 : per_block > 16 ? 16 : per_block;
