@@ -25,6 +25,17 @@ namespace hexval {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// The same address as a global-memory pointer.  Mesh records read from the
+// batch table reach the kernels as plain pointers; without the address space
+// their loads and stores compile to flat instructions, which also count
+// against the LDS and scalar-load counter and so stall every LDS wait behind
+// them.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* global(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 __device__ __forceinline__ int lane_rank(uint64_t mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -83,9 +94,10 @@ __device__ __forceinline__ void load_points_t(const MeshDev& m, int64_t e, V3 p[
     const bool conn = G == kGatherAny ? m.conn != nullptr : G != kGatherPoints;
     const bool validate = G == kGatherAny ? m.validate != 0 : G == kGatherChecked;
     if (conn) {
-        const int4* cp = reinterpret_cast<const int4*>(m.conn + 8 * e);
-        const int4 q0 = cp[0], q1 = cp[1];
-        const int idx[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+        const auto* row = global(m.conn) + 8 * e;
+        int idx[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) idx[k] = row[k];
         if (validate) {
 #pragma unroll
             for (int k = 0; k < 8; ++k)
@@ -94,11 +106,11 @@ __device__ __forceinline__ void load_points_t(const MeshDev& m, int64_t e, V3 p[
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const double* v = m.points + 3 * (int64_t)idx[k];
+            const auto* v = global(m.points) + 3 * (int64_t)idx[k];
             p[k] = {v[0], v[1], v[2]};
         }
     } else {
-        const double* v = m.points + 24 * e;
+        const auto* v = global(m.points) + 24 * e;
 #pragma unroll
         for (int k = 0; k < 8; ++k) p[k] = {v[3 * k], v[3 * k + 1], v[3 * k + 2]};
     }
@@ -176,8 +188,8 @@ __device__ void finish_element(const MeshDev& m, int mesh_idx, int64_t e, bool a
     }
     if (pmask | xmask) wave_count(&q.cnt->n_deferred, deferred);
     if (active) {
-        m.verdict[e] = v;
-        if (m.min_coeff) m.min_coeff[e] = bad ? __builtin_nan("") : mn;
+        *global(m.verdict + e) = v;
+        if (m.min_coeff) *global(m.min_coeff + e) = bad ? __builtin_nan("") : mn;
     }
 }
 
@@ -359,12 +371,88 @@ __device__ __forceinline__ void conn_prefetch_loop(const int32_t* conn, int64_t 
     }
 }
 
+// A 64-bit value that every lane of the wave holds, as a scalar.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ void gather8(const double* points, const int idx[8], V3 p[8])
 {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const double* v = points + 3 * (int64_t)idx[k];
+        const auto* v = global(points) + 3 * (int64_t)idx[k];
         p[k] = {v[0], v[1], v[2]};
+    }
+}
+
+// conn_prefetch_loop for a batch whose meshes all have trusted connectivity.
+// The mesh of a tile comes from the tile -> mesh table; the next tile's mesh
+// is looked up (scalar loads, which often miss) while the current tile's
+// vertex loads are in flight, and its rows are prefetched right after.
+// finish(m, mi, e, active, p) runs once the vertices p of element e of mesh
+// m (index mi) have landed.
+template <typename Finish>
+__device__ __forceinline__ void batch_prefetch_loop(const MeshDev* meshes, const int32_t* tile_mesh, TileSched& ts,
+                                                    int4* stage, Finish finish)
+{
+    const int wave_base = threadIdx.x & ~63;
+    // scalar loads: both tables are written before the launch and only read here
+    typedef __attribute__((address_space(4))) const int32_t* const_i32;
+    typedef __attribute__((address_space(4))) const uint64_t* const_u64;
+    static_assert(sizeof(MeshDev) == 64, "mesh record of 8 words");
+    auto mesh_of = [&](int64_t t, int& mi) {
+        mi = ((const_i32)tile_mesh)[(int64_t)uniform_u64((uint64_t)t)];
+        const const_u64 w = (const_u64)(meshes + mi);
+        uint64_t words[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) words[i] = w[i];
+        MeshDev r;
+        __builtin_memcpy(&r, words, sizeof r);
+        return r;
+    };
+    auto prefetch = [&](int64_t t, const MeshDev& m) {
+        int64_t e = (t - m.tile_begin) * (int64_t)blockDim.x + threadIdx.x;
+        e = e < m.n ? e : m.n - 1;    // past the end: a valid row of the same mesh, ignored
+        const int* src = m.conn + 8 * e;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            __builtin_amdgcn_global_load_lds(src + 4 * h, (lds_ptr)&stage[h * 256 + wave_base], 16, 0, 0);
+    };
+    int mi = 0;
+    MeshDev m{};
+    int64_t t = ts.next_tile();
+    if (t >= 0) {
+        m = mesh_of(t, mi);
+        prefetch(t, m);
+    }
+    wait_vmem();
+    while (t >= 0) {
+        const int64_t e = (t - m.tile_begin) * (int64_t)blockDim.x + threadIdx.x;
+        int idx[8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int4 c = stage[h * 256 + threadIdx.x];
+            idx[4 * h] = c.x;
+            idx[4 * h + 1] = c.y;
+            idx[4 * h + 2] = c.z;
+            idx[4 * h + 3] = c.w;
+        }
+        const int64_t tn = ts.next_tile();
+        V3 p[8];
+        gather8(m.points, idx, p);     // every lane holds a valid row
+        int mi_n = mi;
+        MeshDev mn = m;
+        if (tn >= 0) mn = mesh_of(tn, mi_n);
+        wait_lds();                    // the slots are free: every lane has read its row
+        prefetch(tn >= 0 ? tn : t, mn);
+        wait_vmem();                   // vertices and the next rows have landed
+        finish(m, mi, e, e < m.n, p);
+        t = tn;
+        m = mn;
+        mi = mi_n;
     }
 }
 
@@ -381,6 +469,19 @@ __global__ __launch_bounds__(256) void k_top_f64_conn(TopArgs a)
         gather8(m.points, idx, p);
         wait_vmem();                   // vertices and the next rows have landed
         finish_element<EDGES>(m, 0, e, active, p, false, a.q, a.max_depth);
+    });
+}
+
+// k_top_f64_range for a batch whose meshes all have trusted connectivity,
+// through batch_prefetch_loop.
+template <bool EDGES>
+__global__ __launch_bounds__(256) void k_top_f64_batch_conn(TopArgs a)
+{
+    __shared__ int4 stage[2 * 256];
+    TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
+    batch_prefetch_loop(a.meshes, a.tile_mesh, ts, stage,
+                        [&](const MeshDev& m, int mi, int64_t e, bool active, const V3* p) {
+        finish_element<EDGES>(m, mi, e, active, p, false, a.q, a.max_depth);
     });
 }
 
@@ -464,8 +565,8 @@ __device__ void filter_finish(const MeshDev& m, int mesh_idx, int64_t e, bool ac
         wave_count(&q.cnt->n_deferred, deferred);
     }
     if (active) {
-        m.verdict[e] = v;
-        if (m.min_coeff && !recheck) m.min_coeff[e] = bad ? __builtin_nan("") : (double)mn;
+        *global(m.verdict + e) = v;
+        if (m.min_coeff && !recheck) *global(m.min_coeff + e) = bad ? __builtin_nan("") : (double)mn;
     }
 }
 
@@ -511,6 +612,18 @@ __global__ __launch_bounds__(256) void k_filter_f32_conn(TopArgs a)
         gather8(m.points, idx, p);
         wait_vmem();
         filter_finish(m, 0, e, active, p, false, a.q);
+    });
+}
+
+// k_filter_f32_range for a batch whose meshes all have trusted
+// connectivity, through batch_prefetch_loop.
+__global__ __launch_bounds__(256) void k_filter_f32_batch_conn(TopArgs a)
+{
+    __shared__ int4 stage[2 * 256];
+    TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
+    batch_prefetch_loop(a.meshes, a.tile_mesh, ts, stage,
+                        [&](const MeshDev& m, int mi, int64_t e, bool active, const V3* p) {
+        filter_finish(m, mi, e, active, p, false, a.q);
     });
 }
 
@@ -1366,7 +1479,9 @@ void launch_top_range(const TopArgs& a, bool batched, int grid, int block, hipSt
 {
     const bool edges = a.max_depth == 0;
     if (batched) {
-        if (edges) HX_LAUNCH((k_top_f64_range<true, true, kGatherAny>), grid, block, s, a);
+        if (a.batch_conn && edges) HX_LAUNCH((k_top_f64_batch_conn<true>), grid, block, s, a);
+        else if (a.batch_conn) HX_LAUNCH((k_top_f64_batch_conn<false>), grid, block, s, a);
+        else if (edges) HX_LAUNCH((k_top_f64_range<true, true, kGatherAny>), grid, block, s, a);
         else HX_LAUNCH((k_top_f64_range<true, false, kGatherAny>), grid, block, s, a);
         return;
     }
@@ -1387,7 +1502,8 @@ void launch_top_range(const TopArgs& a, bool batched, int grid, int block, hipSt
 void launch_filter_range(const TopArgs& a, bool batched, int grid, int block, hipStream_t s)
 {
     if (batched) {
-        HX_LAUNCH((k_filter_f32_range<true, kGatherAny>), grid, block, s, a);
+        if (a.batch_conn) HX_LAUNCH(k_filter_f32_batch_conn, grid, block, s, a);
+        else HX_LAUNCH((k_filter_f32_range<true, kGatherAny>), grid, block, s, a);
         return;
     }
     if (!a.mesh.conn) HX_LAUNCH((k_filter_f32_range<false, kGatherPoints>), grid, block, s, a);

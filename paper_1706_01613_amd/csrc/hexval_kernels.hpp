@@ -16,6 +16,8 @@ struct TopArgs {
     QueueDev q;
     int32_t max_depth;
     int32_t xcds;                         // tile chunks (1 or 8)
+    int32_t batch_conn;                   // batched: every mesh with tiles has trusted connectivity
+    int32_t pad;
 };
 
 struct LevelArgs {

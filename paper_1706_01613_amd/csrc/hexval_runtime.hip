@@ -488,7 +488,12 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     // Launch shape of the first pass: explicit options, else the tuning cache,
     // else (autotuning on) measured below on this input, else defaults.
     TuneChoice choice;
-    const int gather = batched ? 0 : !meshes[0].connectivity ? 1 : (o.validate_indices ? 3 : 2);
+    // a batch whose non-empty meshes all have trusted connectivity takes the
+    // prefetching first pass (its own tuning key)
+    bool batch_conn = batched && !o.validate_indices;
+    for (int i = 0; batch_conn && i < n_meshes; ++i)
+        if (meshes[i].n > 0 && !meshes[i].connectivity) batch_conn = false;
+    const int gather = batched ? (batch_conn ? 4 : 0) : !meshes[0].connectivity ? 1 : (o.validate_indices ? 3 : 2);
     std::string key;
     bool need_tune = false;
     if (o.block_threads || o.grid_blocks) {
@@ -573,6 +578,7 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         ta.q = q;
         ta.max_depth = o.max_depth;
         ta.xcds = xcds;
+        ta.batch_conn = batch_conn ? 1 : 0;
         return ta;
     };
     auto launch_first = [&](const TopArgs& ta, int64_t g, int blk) {

@@ -62,6 +62,33 @@ def test_batched_equals_alone_and_oracle(precision):
                       Vh, Ch, label=f"mesh {k}")
 
 
+@pytest.mark.parametrize("precision", [hx.FP64, hx.FP32_FILTER])
+def test_batched_connectivity_meshes_equal_alone(precision):
+    # every non-empty mesh has trusted connectivity: the first pass
+    # prefetches each tile's rows, looking the tile's mesh up first; ragged
+    # meshes (many smaller than a tile), empty ones, several launch shapes
+    # and the depth-0 variant (edge values in step 2)
+    torch = torch_cuda()
+    _say(f"batched connectivity-only meshes, precision {precision}")
+    meshes = list(synth.batched_meshes_torch(90, lo=0.0, hi=4.2, seed=21))
+    empty = (torch.empty((0, 3), dtype=torch.float64, device="cuda"),
+             torch.empty((0, 8), dtype=torch.int32, device="cuda"))
+    meshes.insert(0, empty)
+    meshes.insert(40, empty)
+    meshes.append(empty)
+    for kw in [{}, {"block_threads": 64, "grid_blocks": 48}, {"block_threads": 128}, {"max_depth": 0}]:
+        vs, ms = _batched(torch, meshes, precision, **kw)
+        for k, ((V, C), v, m) in enumerate(zip(meshes, vs, ms)):
+            va, ma = _alone(torch, V, C, precision=precision, **kw)
+            assert torch.equal(v, va), (k, kw)
+            assert torch.equal(torch.nan_to_num(m, 7.0), torch.nan_to_num(ma, 7.0)), (k, kw)
+    vs, ms = _batched(torch, meshes, precision)
+    for k in (1, 17, 52, len(meshes) - 2):
+        V, C = meshes[k]
+        assert_parity(vs[k].cpu().numpy(), ms[k].cpu().numpy() if precision == hx.FP64 else None,
+                      V.cpu().numpy(), C.cpu().numpy(), label=f"mesh {k}")
+
+
 def test_launch_shape_does_not_change_results():
     torch = torch_cuda()
     V, C = synth.warped_lattice_torch(60, 50, 40, jitter=0.4, seed=3)
