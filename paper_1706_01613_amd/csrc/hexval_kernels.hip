@@ -132,14 +132,91 @@ __device__ void write_root(Node* nd, const ElementValues& r, int64_t slot)
     nd->orient = 0;
 }
 
-// One element: decides, writes outputs, takes part in the wave's compaction
-// of subdivided and exact-tier elements into their lists (every lane of the
-// wave must call this).  Subdivided elements only get their id listed here;
+// Slot (in order of waves, then lanes) for each thread of the block with
+// `want`, from one atomic on *c per block.  Every thread of the block calls
+// it (it synchronizes the block).
+__device__ unsigned long long block_reserve(unsigned long long* c, bool want)
+{
+    __shared__ unsigned int wave_want[4];
+    __shared__ unsigned long long base;
+    const int wid = threadIdx.x >> 6;
+    const uint64_t mask = ballot(want);
+    if ((threadIdx.x & 63) == 0) wave_want[wid] = (unsigned int)__popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int total = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) total += wave_want[w];
+        base = total ? atomicAdd(c, (unsigned long long)total) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long off = base + (unsigned long long)lane_rank(mask);
+    for (int w = 0; w < wid; ++w) off += wave_want[w];
+    __syncthreads();   // wave_want and base are rewritten by the next call
+    return off;
+}
+
+// Orders this wave's LDS writes before its later LDS reads by other lanes
+// (a compiler barrier: one wave's LDS accesses complete in issue order).
+__device__ __forceinline__ void lds_order() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
+// Elements the first pass sends to subdivision are held per wave in LDS and
+// appended to the subdivision list up to kPushBuf at a time, with one atomic:
+// on invalid-heavy meshes most waves send some element, and one atomic per
+// wave and tile on the single list counter serialises the pass.  Their
+// verdict (pending, or deferred when the list is full) is written when they
+// are appended.  Every lane of the wave calls push_flush; each kernel that
+// fills a buffer flushes it after its last tile.
+constexpr int kPushBuf = 256;
+
+struct PushBuf {
+    __attribute__((address_space(3))) int64_t* elem;   // this wave's kPushBuf entries
+    __attribute__((address_space(3))) int32_t* mesh;
+    int n;                                              // entries held (wave-uniform)
+};
+
+#define HX_PUSH_STORAGE                                              \
+    __shared__ int64_t push_elem_[4 * kPushBuf];                     \
+    __shared__ int32_t push_mesh_[4 * kPushBuf];                     \
+    PushBuf pb{(__attribute__((address_space(3))) int64_t*)(push_elem_ + (threadIdx.x >> 6) * kPushBuf), \
+               (__attribute__((address_space(3))) int32_t*)(push_mesh_ + (threadIdx.x >> 6) * kPushBuf), 0}
+
+// meshes: the batch table, or nullptr when every entry belongs to `single`.
+__device__ void push_flush(PushBuf& pb, const QueueDev& q, const MeshDev& single, const MeshDev* meshes)
+{
+    if (pb.n == 0) return;
+    const int lane = threadIdx.x & 63;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&q.cnt->n_sub, (unsigned long long)pb.n);
+    base = wave_bcast(base, 0);
+    lds_order();                       // the entries other lanes wrote are visible
+    unsigned long long deferred = 0;
+    for (int i = lane; i < pb.n; i += 64) {
+        const int64_t e = pb.elem[i];
+        const int mi = pb.mesh[i];
+        uint8_t* verdict = meshes ? meshes[mi].verdict : single.verdict;
+        const unsigned long long slot = base + (unsigned long long)i;
+        if (slot < q.node_cap) {
+            q.sub_elem[slot] = e;
+            q.sub_mesh[slot] = mi;
+            *global(verdict + e) = kPending;
+        } else {
+            *global(verdict + e) = kDeferred;
+            ++deferred;
+        }
+    }
+    if (deferred) atomicAdd(&q.cnt->n_deferred, deferred);
+    lds_order();                       // reads done before the buffer is refilled
+    pb.n = 0;
+}
+
+// One element: decides, writes outputs, takes part in the compaction of
+// subdivided and exact-tier elements into their lists (every thread of the
+// block must call this: the subdivision list is reserved per block).  Subdivided elements only get their id listed here;
 // k_roots recomputes their 27 coefficients, which keeps this kernel's
 // register footprint small.
 template <bool EDGES>
 __device__ void finish_element(const MeshDev& m, int mesh_idx, int64_t e, bool active, const V3 p[8],
-                               bool bad, const QueueDev& q, int max_depth)
+                               bool bad, const QueueDev& q, int max_depth, PushBuf& pb, const MeshDev* meshes)
 {
     int st = -1;
     double mn = 0.0;
@@ -158,18 +235,13 @@ __device__ void finish_element(const MeshDev& m, int mesh_idx, int64_t e, bool a
     bool deferred = false;
     const bool push = active && st == kTopSubdivide;
     const uint64_t pmask = ballot(push);
-    if (pmask) {
-        const unsigned long long slot = wave_reserve(&q.cnt->n_sub, pmask);
+    if (pmask) {                       // room for 64: flushed below once fuller
         if (push) {
-            if (slot < q.node_cap) {
-                q.sub_elem[slot] = e;
-                q.sub_mesh[slot] = mesh_idx;
-                v = kPending;
-            } else {
-                v = kDeferred;
-                deferred = true;
-            }
+            const int k = pb.n + lane_rank(pmask);
+            pb.elem[k] = e;
+            pb.mesh[k] = mesh_idx;
         }
+        pb.n += __popcll(pmask);
     }
     const bool exact = active && st == kTopExact;
     const uint64_t xmask = ballot(exact);
@@ -186,21 +258,22 @@ __device__ void finish_element(const MeshDev& m, int mesh_idx, int64_t e, bool a
             }
         }
     }
-    if (pmask | xmask) wave_count(&q.cnt->n_deferred, deferred);
+    if (xmask) wave_count(&q.cnt->n_deferred, deferred);
     if (active) {
-        *global(m.verdict + e) = v;
+        if (!push) *global(m.verdict + e) = v;   // listed elements: at push_flush
         if (m.min_coeff) *global(m.min_coeff + e) = bad ? __builtin_nan("") : mn;
     }
+    if (pb.n > kPushBuf - 64) push_flush(pb, q, m, meshes);
 }
 
 template <bool EDGES, int G>
 __device__ void process_element(const MeshDev& m, int mesh_idx, int64_t e, bool active,
-                                const QueueDev& q, int max_depth)
+                                const QueueDev& q, int max_depth, PushBuf& pb, const MeshDev* meshes)
 {
     V3 p[8];
     bool bad = false;
     if (active) load_points_t<G>(m, e, p, bad);
-    finish_element<EDGES>(m, mesh_idx, e, active, p, bad, q, max_depth);
+    finish_element<EDGES>(m, mesh_idx, e, active, p, bad, q, max_depth, pb, meshes);
 }
 
 // Root nodes of the subdivided elements listed by the first pass: the full
@@ -295,6 +368,7 @@ struct TileSched {
 template <bool BATCHED, bool EDGES, int G>
 __global__ __launch_bounds__(256) void k_top_f64_range(TopArgs a)
 {
+    HX_PUSH_STORAGE;
     TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
     for (int64_t t = ts.next_tile(); t >= 0; t = ts.next_tile()) {
         MeshDev m;
@@ -309,8 +383,9 @@ __global__ __launch_bounds__(256) void k_top_f64_range(TopArgs a)
             m = a.mesh;
             e = t * (int64_t)blockDim.x + threadIdx.x;
         }
-        process_element<EDGES, G>(m, mi, e, e < m.n, a.q, a.max_depth);
+        process_element<EDGES, G>(m, mi, e, e < m.n, a.q, a.max_depth, pb, BATCHED ? a.meshes : nullptr);
     }
+    push_flush(pb, a.q, a.mesh, BATCHED ? a.meshes : nullptr);
 }
 
 // LDS address space pointer, as the direct global-to-LDS loads take it.
@@ -459,35 +534,40 @@ __device__ __forceinline__ void batch_prefetch_loop(const MeshDev* meshes, const
 // k_top_f64_range for a single mesh with trusted connectivity, through
 // conn_prefetch_loop.
 template <bool EDGES>
-__global__ __launch_bounds__(256) void k_top_f64_conn(TopArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_top_f64_conn(TopArgs a)
 {
     __shared__ int4 stage[2 * 256];
+    HX_PUSH_STORAGE;
     const MeshDev& m = a.mesh;
     TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
     conn_prefetch_loop<8>(m.conn, m.n, ts, stage, [&](int64_t e, bool active, const int* idx) {
         V3 p[8];
         gather8(m.points, idx, p);
         wait_vmem();                   // vertices and the next rows have landed
-        finish_element<EDGES>(m, 0, e, active, p, false, a.q, a.max_depth);
+        finish_element<EDGES>(m, 0, e, active, p, false, a.q, a.max_depth, pb, nullptr);
     });
+    push_flush(pb, a.q, m, nullptr);
 }
 
 // k_top_f64_range for a batch whose meshes all have trusted connectivity,
 // through batch_prefetch_loop.
 template <bool EDGES>
-__global__ __launch_bounds__(256) void k_top_f64_batch_conn(TopArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_top_f64_batch_conn(TopArgs a)
 {
     __shared__ int4 stage[2 * 256];
+    HX_PUSH_STORAGE;
     TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
     batch_prefetch_loop(a.meshes, a.tile_mesh, ts, stage,
                         [&](const MeshDev& m, int mi, int64_t e, bool active, const V3* p) {
-        finish_element<EDGES>(m, mi, e, active, p, false, a.q, a.max_depth);
+        finish_element<EDGES>(m, mi, e, active, p, false, a.q, a.max_depth, pb, a.meshes);
     });
+    push_flush(pb, a.q, a.mesh, a.meshes);
 }
 
 template <bool BATCHED, bool EDGES>
 __global__ __launch_bounds__(256) void k_top_f64_list(TopArgs a)
 {
+    HX_PUSH_STORAGE;
     const unsigned long long cnt = *a.list_count;
     const int64_t n = (int64_t)(cnt < a.q.list_cap ? cnt : a.q.list_cap);
     const int64_t n_tiles = (n + blockDim.x - 1) / blockDim.x;
@@ -501,36 +581,15 @@ __global__ __launch_bounds__(256) void k_top_f64_list(TopArgs a)
             mi = a.q.list_mesh[i];
         }
         const MeshDev m = BATCHED && active ? a.meshes[mi] : a.mesh;
-        process_element<EDGES, kGatherAny>(m, mi, e, active, a.q, a.max_depth);
+        process_element<EDGES, kGatherAny>(m, mi, e, active, a.q, a.max_depth, pb, BATCHED ? a.meshes : nullptr);
     }
+    push_flush(pb, a.q, a.mesh, BATCHED ? a.meshes : nullptr);
 }
 
 // FP32 filter, one element per lane: certain INVALID / VALID elements are
 // final here (min_coeff is the FP32 minimum, widened); every other element
 // is listed for the FP64 pass (k_top_f64_list), which decides it exactly as
 // the plain FP64 path would.
-// Slot (in order of waves, then lanes) for each thread of the block with
-// `want`, from one atomic on *c per block.  Every thread of the block calls
-// it (it synchronizes the block).
-__device__ unsigned long long block_reserve(unsigned long long* c, bool want)
-{
-    __shared__ unsigned int wave_want[4];
-    __shared__ unsigned long long base;
-    const int wid = threadIdx.x >> 6;
-    const uint64_t mask = ballot(want);
-    if ((threadIdx.x & 63) == 0) wave_want[wid] = (unsigned int)__popcll(mask);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned int total = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) total += wave_want[w];
-        base = total ? atomicAdd(c, (unsigned long long)total) : 0ull;
-    }
-    __syncthreads();
-    unsigned long long off = base + (unsigned long long)lane_rank(mask);
-    for (int w = 0; w < wid; ++w) off += wave_want[w];
-    __syncthreads();   // wave_want and base are rewritten by the next call
-    return off;
-}
 
 // Every thread of the block calls this (block-level list reservation: one
 // atomic per block and tile instead of one per wave, which matters when
@@ -655,9 +714,6 @@ __device__ LevelRange level_range(const Counters* cnt, int L, uint64_t cap)
     return {base, count, base + count};
 }
 
-// Orders this wave's LDS writes before its later LDS reads by other lanes
-// (a compiler barrier: one wave's LDS accesses complete in issue order).
-__device__ __forceinline__ void lds_order() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
 
 constexpr int kNodeWords = 30;   // words of a Node that carry data
 
