@@ -392,7 +392,7 @@ static int exact_tier(Workspace& w, const double* pts, uint8_t* v, uint8_t* hv, 
 
 struct TuneChoice {
     int block = 256;
-    int per_cu = 16;   // persistent grid of per_cu blocks per CU (tiles are handed out at run time)
+    int per_cu = 4;    // persistent grid of per_cu blocks per CU (tiles are handed out at run time)
 };
 
 static std::mutex g_tune_mu;
@@ -459,7 +459,7 @@ int run_check(const hexval_mesh_t* meshes, int n_meshes, bool batched, const hex
 }
 
 int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const hexval_opts_t* opts_in,
-                 uint8_t* const* verdicts, double* const* mins, Workspace* fixed)
+                 uint8_t* const* verdicts, double* const* mins, Workspace* fixed, bool tune)
 {
     hexval_opts_t o;
     if (opts_in) o = *opts_in;
@@ -504,7 +504,7 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         tune_load_locked();
         auto it = g_tune.find(key);
         if (it != g_tune.end()) choice = it->second;
-        else need_tune = autotune_enabled();
+        else need_tune = tune && autotune_enabled();
     }
     // Automatic queue size: 1/32 of the elements, at least 2^19 nodes (any
     // single element's tree at the default cap fits), and room for a tree

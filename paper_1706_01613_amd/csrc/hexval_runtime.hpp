@@ -63,9 +63,11 @@ void release_workspace(Workspace* w);
 int run_check(const hexval_mesh_t* meshes, int n_meshes, bool batched, const hexval_opts_t* opts,
               uint8_t* const* verdicts, double* const* mins);
 
-// Same, on a caller-owned workspace (nullptr: one from the pool).
+// Same, on a caller-owned workspace (nullptr: one from the pool).  tune:
+// whether a launch shape not in the tuning cache may be timed on this call
+// (else the default shape is used).
 int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const hexval_opts_t* opts,
-                 uint8_t* const* verdicts, double* const* mins, Workspace* ws);
+                 uint8_t* const* verdicts, double* const* mins, Workspace* ws, bool tune = true);
 
 // Corner-only test and corner quality (hexval_corner_test).
 int run_corner_test(const hexval_mesh_t* mesh, const hexval_opts_t* opts, uint8_t* test1, double* quality);

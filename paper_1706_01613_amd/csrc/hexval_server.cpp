@@ -1,13 +1,18 @@
 // Request queue with continuous batching (hexval_server_* of hexval.h).
 //
 // max_slots worker threads, each with its own HIP stream and its own
-// workspace (subdivision queue and lists allocated once, at creation, and
-// counted against the HBM budget).  A worker that becomes free admits the
-// oldest waiting request if its device footprint (the mesh bytes the server
-// must upload, zero for a device-resident mesh) fits what is left of the
-// budget; admitted requests run concurrently on their streams, so requests
-// arriving while others are on the GPU join as soon as a slot and memory are
-// free.  The arithmetic of an element never depends on the batch it runs in.
+// workspace (subdivision queue and lists, and the tables of a batch of up to
+// kMaxBatch meshes, allocated once, at creation, and counted against the HBM
+// budget).  A worker that becomes free admits the oldest waiting request if
+// its device footprint (the mesh bytes the server must upload, zero for a
+// device-resident mesh) fits what is left of the budget.  When that request
+// is device-resident, the worker also takes the device-resident requests
+// queued right behind it, up to kMaxBatch of them and kBatchHexes elements
+// in all, and runs them as one batched call: under load the per-call launch
+// and synchronisation costs are shared.  Admitted work runs concurrently on
+// the slots' streams, so requests arriving while others are on the GPU join
+// as soon as a slot and memory are free.  The arithmetic of an element never
+// depends on the batch it runs in.
 #include <hip/hip_runtime.h>
 
 #include <string.h>
@@ -30,6 +35,9 @@
 using Clock = std::chrono::steady_clock;
 
 namespace hexval {
+
+constexpr int kMaxBatch = 64;                 // requests per batched call
+constexpr int64_t kBatchHexes = 1ll << 24;    // elements per batched call
 
 struct ServerRequest {
     uint64_t ticket = 0;
@@ -114,14 +122,32 @@ static int run_one(hexval_server* sv, Slot& sl, ServerRequest& rq)
     hexval_opts_t o = sv->opts;
     o.stream = sl.stream;
     o.stats = nullptr;
-    return run_check_ws(&m, 1, false, &o, &r.verdicts, &r.min_coeffs, sl.ws);
+    // shapes are timed by direct calls only: timing one here would stall the slot
+    return run_check_ws(&m, 1, false, &o, &r.verdicts, &r.min_coeffs, sl.ws, false);
+}
+
+// Device-resident requests as one batched call.
+static int run_batch(hexval_server* sv, Slot& sl, const std::vector<ServerRequest*>& batch)
+{
+    std::vector<hexval_mesh_t> meshes;
+    std::vector<uint8_t*> verdicts;
+    std::vector<double*> mins;
+    for (ServerRequest* rq : batch) {
+        meshes.push_back(rq->req.mesh);
+        verdicts.push_back(rq->req.verdicts);
+        mins.push_back(rq->req.min_coeffs);
+    }
+    hexval_opts_t o = sv->opts;
+    o.stream = sl.stream;
+    o.stats = nullptr;
+    return run_check_ws(meshes.data(), (int)meshes.size(), true, &o, verdicts.data(), mins.data(), sl.ws, false);
 }
 
 static void worker_loop(hexval_server* sv, Slot* sl)
 {
     hipSetDevice(sv->device);
     for (;;) {
-        ServerRequest* rq = nullptr;
+        std::vector<ServerRequest*> batch;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
             sv->cv_work.wait(lk, [&] {
@@ -130,19 +156,36 @@ static void worker_loop(hexval_server* sv, Slot* sl)
                 return sv->in_use + (int64_t)sv->pending.front()->upload_bytes <= sv->budget - sv->reserved;
             });
             if (sv->pending.empty()) return;
-            rq = sv->pending.front();
+            ServerRequest* rq = sv->pending.front();
             sv->pending.pop_front();
             sv->in_use += (int64_t)rq->upload_bytes;
+            batch.push_back(rq);
+            // device-resident requests queued behind it join its call (in
+            // order: the first one that needs an upload, or would overflow
+            // the batch, stops the batch)
+            int64_t hexes = rq->req.mesh.n;
+            if (rq->upload_bytes == 0 && hexes <= kBatchHexes) {
+                while (!sv->pending.empty() && (int)batch.size() < kMaxBatch) {
+                    ServerRequest* nx = sv->pending.front();
+                    if (nx->upload_bytes != 0 || hexes + nx->req.mesh.n > kBatchHexes) break;
+                    sv->pending.pop_front();
+                    batch.push_back(nx);
+                    hexes += nx->req.mesh.n;
+                }
+            }
         }
-        const int st = run_one(sv, *sl, *rq);
+        const int st = batch.size() == 1 ? run_one(sv, *sl, *batch[0]) : run_batch(sv, *sl, batch);
         const std::string err = st ? last_error() : "";
         {
             std::lock_guard<std::mutex> lk(sv->mu);
-            sv->in_use -= (int64_t)rq->upload_bytes;
-            rq->status = st;
-            rq->error = err;
-            rq->t_done = Clock::now();
-            rq->done = true;
+            const auto now = Clock::now();
+            for (ServerRequest* rq : batch) {
+                sv->in_use -= (int64_t)rq->upload_bytes;
+                rq->status = st;
+                rq->error = err;
+                rq->t_done = now;
+                rq->done = true;
+            }
         }
         sv->cv_done.notify_all();
         sv->cv_work.notify_all();
@@ -171,7 +214,9 @@ int hexval_server_create(const hexval_opts_t* opts, int64_t hbm_budget_bytes, in
     if ((rc = current_device(&dev, &cus))) return rc;
     const uint64_t node_cap = o.queue_capacity ? (uint64_t)o.queue_capacity : (1ull << 20);
     const uint64_t list_cap = o.precision == HEXVAL_FP32_FILTER ? (1ull << 22) : std::max<uint64_t>(node_cap, 1u << 16);
-    const int64_t per_slot = (int64_t)Workspace::footprint(node_cap, list_cap, 1, 1);
+    // batch tables: tiles of at least 64 elements, one partial tile per mesh
+    const uint64_t batch_tiles = (uint64_t)(kBatchHexes / 64 + kMaxBatch);
+    const int64_t per_slot = (int64_t)Workspace::footprint(node_cap, list_cap, kMaxBatch, batch_tiles);
     if (per_slot * max_slots > hbm_budget_bytes)
         return fail(HEXVAL_E_ARG, "budget %lld B is below the %d slot workspaces (%lld B each)",
                     (long long)hbm_budget_bytes, max_slots, (long long)per_slot);
@@ -186,7 +231,7 @@ int hexval_server_create(const hexval_opts_t* opts, int64_t hbm_budget_bytes, in
             return fail(HEXVAL_E_HIP, "hipStreamCreate failed");
         sl->ws = new Workspace();
         sl->ws->device = dev;
-        if ((rc = sl->ws->init()) || (rc = sl->ws->ensure(node_cap, list_cap, 1, 1))) {
+        if ((rc = sl->ws->init()) || (rc = sl->ws->ensure(node_cap, list_cap, kMaxBatch, batch_tiles))) {
             delete sl->ws;
             hipStreamDestroy(sl->stream);
             return rc;
