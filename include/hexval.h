@@ -241,13 +241,17 @@ int hexval_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts, do
                         double* lo, double* hi, uint8_t* status);
 
 /* ---- request queue with continuous batching --------------------------------
- * A server runs a scheduler thread that admits submitted requests while fewer
- * than max_slots are in flight and their device footprint fits the HBM budget,
- * and runs admitted requests concurrently on separate HIP streams.  A request
- * whose mesh pointers are device pointers references that memory (the caller
- * keeps it alive until the request is done); with host_points/host_conn set
- * the server copies the mesh to the device itself (pinned staging, copy
- * stream) and counts that copy in the footprint. */
+ * A server runs max_slots worker threads, each with its own HIP stream.  A
+ * free worker admits the oldest submitted request if its device footprint
+ * fits the HBM budget; when that request is device-resident, the
+ * device-resident requests queued right behind it (up to 64 requests and
+ * 2^24 elements in all) join it in one batched call.  Admitted work runs
+ * concurrently on the workers' streams.  Outputs never depend on how
+ * requests were grouped.  A request whose mesh pointers are device pointers
+ * references that memory (the caller keeps it alive until the request is
+ * done); with host_points/host_conn set the server copies the mesh to the
+ * device itself (pinned staging, copy stream) and counts that copy in the
+ * footprint. */
 typedef struct hexval_server hexval_server_t;
 
 typedef struct {
