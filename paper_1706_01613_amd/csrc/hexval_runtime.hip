@@ -645,10 +645,10 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         }
         if (timing && round == 0) HX_HIP(hipEventRecord(w.ev[1], s));
         HX_HIP(hipGetLastError());
-        HX_HIP(hipMemcpyAsync(w.hcnt, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-        HX_HIP(hipStreamSynchronize(s));
-        // Subdivision only when the first pass listed elements for it.
-        if (w.hcnt->n_sub > 0) {
+        // Subdivision follows without a host round trip: its kernels read the
+        // list sizes on the device and do nothing when the list is empty
+        // (cheaper than waiting for the counters whenever it is not).
+        {
             RootArgs ra{q, single, dmeshes};
             launch_roots(ra, cus * 2, s);
             for (int L = 0; L < o.max_depth; ++L) {
