@@ -805,9 +805,8 @@ int run_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts_in, do
         launch_minj_top(a, cus * 8, s);
         if (timing && round == 0) HX_HIP(hipEventRecord(w.ev[1], s));
         HX_HIP(hipGetLastError());
-        HX_HIP(hipMemcpyAsync(w.hcnt, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-        HX_HIP(hipStreamSynchronize(s));
-        if (w.hcnt->n_sub > 0) {
+        // subdivision follows on the device (empty lists do nothing)
+        {
             launch_minj_roots(a, cus * 2, s);
             for (int L = 0; L <= o.max_depth; ++L) {
                 a.level = L;
