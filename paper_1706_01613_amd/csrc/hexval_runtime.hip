@@ -458,6 +458,10 @@ int run_check(const hexval_mesh_t* meshes, int n_meshes, bool batched, const hex
     return run_check_ws(meshes, n_meshes, batched, opts, verdicts, mins, nullptr);
 }
 
+// Calls of at least this many elements launch subdivision without first
+// reading the counters back.
+constexpr int64_t kEagerSubdivision = 1ll << 20;
+
 int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const hexval_opts_t* opts_in,
                  uint8_t* const* verdicts, double* const* mins, Workspace* fixed, bool tune)
 {
@@ -645,10 +649,18 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         }
         if (timing && round == 0) HX_HIP(hipEventRecord(w.ev[1], s));
         HX_HIP(hipGetLastError());
-        // Subdivision follows without a host round trip: its kernels read the
-        // list sizes on the device and do nothing when the list is empty
-        // (cheaper than waiting for the counters whenever it is not).
-        {
+        // Subdivision: its kernels read the list sizes on the device and do
+        // nothing when the list is empty.  Large calls launch it right away
+        // (a host round trip costs more than the launches, and such meshes
+        // usually list some element); small ones read the counters first and
+        // skip it when nothing was listed.
+        bool subdivide = true;
+        if (total < kEagerSubdivision) {
+            HX_HIP(hipMemcpyAsync(w.hcnt, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+            HX_HIP(hipStreamSynchronize(s));
+            subdivide = w.hcnt->n_sub > 0;
+        }
+        if (subdivide) {
             RootArgs ra{q, single, dmeshes};
             launch_roots(ra, cus * 2, s);
             for (int L = 0; L < o.max_depth; ++L) {
