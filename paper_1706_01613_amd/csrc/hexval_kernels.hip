@@ -132,29 +132,6 @@ __device__ void write_root(Node* nd, const ElementValues& r, int64_t slot)
     nd->orient = 0;
 }
 
-// Slot (in order of waves, then lanes) for each thread of the block with
-// `want`, from one atomic on *c per block.  Every thread of the block calls
-// it (it synchronizes the block).
-__device__ unsigned long long block_reserve(unsigned long long* c, bool want)
-{
-    __shared__ unsigned int wave_want[4];
-    __shared__ unsigned long long base;
-    const int wid = threadIdx.x >> 6;
-    const uint64_t mask = ballot(want);
-    if ((threadIdx.x & 63) == 0) wave_want[wid] = (unsigned int)__popcll(mask);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned int total = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) total += wave_want[w];
-        base = total ? atomicAdd(c, (unsigned long long)total) : 0ull;
-    }
-    __syncthreads();
-    unsigned long long off = base + (unsigned long long)lane_rank(mask);
-    for (int w = 0; w < wid; ++w) off += wave_want[w];
-    __syncthreads();   // wave_want and base are rewritten by the next call
-    return off;
-}
-
 // Orders this wave's LDS writes before its later LDS reads by other lanes
 // (a compiler barrier: one wave's LDS accesses complete in issue order).
 __device__ __forceinline__ void lds_order() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
@@ -180,13 +157,29 @@ struct PushBuf {
     PushBuf pb{(__attribute__((address_space(3))) int64_t*)(push_elem_ + (threadIdx.x >> 6) * kPushBuf), \
                (__attribute__((address_space(3))) int32_t*)(push_mesh_ + (threadIdx.x >> 6) * kPushBuf), 0}
 
+// A list that buffered entries are appended to: the subdivision list, or
+// the FP32 filter's FP64 recheck list.
+struct ListRef {
+    unsigned long long* count;
+    int64_t* elem;
+    int32_t* mesh;
+    uint64_t cap;
+};
+
+__device__ __forceinline__ ListRef sub_list(const QueueDev& q) { return {&q.cnt->n_sub, q.sub_elem, q.sub_mesh, q.node_cap}; }
+__device__ __forceinline__ ListRef recheck_list(const QueueDev& q)
+{
+    return {&q.cnt->n_list, q.list_elem, q.list_mesh, q.list_cap};
+}
+
 // meshes: the batch table, or nullptr when every entry belongs to `single`.
-__device__ void push_flush(PushBuf& pb, const QueueDev& q, const MeshDev& single, const MeshDev* meshes)
+__device__ void push_flush(PushBuf& pb, const ListRef& l, const QueueDev& q, const MeshDev& single,
+                           const MeshDev* meshes)
 {
     if (pb.n == 0) return;
     const int lane = threadIdx.x & 63;
     unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(&q.cnt->n_sub, (unsigned long long)pb.n);
+    if (lane == 0) base = atomicAdd(l.count, (unsigned long long)pb.n);
     base = wave_bcast(base, 0);
     lds_order();                       // the entries other lanes wrote are visible
     unsigned long long deferred = 0;
@@ -195,9 +188,9 @@ __device__ void push_flush(PushBuf& pb, const QueueDev& q, const MeshDev& single
         const int mi = pb.mesh[i];
         uint8_t* verdict = meshes ? meshes[mi].verdict : single.verdict;
         const unsigned long long slot = base + (unsigned long long)i;
-        if (slot < q.node_cap) {
-            q.sub_elem[slot] = e;
-            q.sub_mesh[slot] = mi;
+        if (slot < l.cap) {
+            l.elem[slot] = e;
+            l.mesh[slot] = mi;
             *global(verdict + e) = kPending;
         } else {
             *global(verdict + e) = kDeferred;
@@ -207,6 +200,21 @@ __device__ void push_flush(PushBuf& pb, const QueueDev& q, const MeshDev& single
     if (deferred) atomicAdd(&q.cnt->n_deferred, deferred);
     lds_order();                       // reads done before the buffer is refilled
     pb.n = 0;
+}
+
+// Adds this wave's lanes with `want` to the buffer, flushing it to list l
+// first when it could overflow.  Every lane of the wave calls this.
+__device__ __forceinline__ void push_entry(PushBuf& pb, const ListRef& l, const QueueDev& q, const MeshDev& single,
+                                           const MeshDev* meshes, bool want, int64_t e, int mesh_idx)
+{
+    const uint64_t mask = ballot(want);
+    if (!mask) return;
+    if (want) {
+        const int k = pb.n + lane_rank(mask);
+        pb.elem[k] = e;
+        pb.mesh[k] = mesh_idx;
+    }
+    pb.n += __popcll(mask);
 }
 
 // One element: decides, writes outputs, takes part in the compaction of
@@ -234,15 +242,7 @@ __device__ void finish_element(const MeshDev& m, int mesh_idx, int64_t e, bool a
     }
     bool deferred = false;
     const bool push = active && st == kTopSubdivide;
-    const uint64_t pmask = ballot(push);
-    if (pmask) {                       // room for 64: flushed below once fuller
-        if (push) {
-            const int k = pb.n + lane_rank(pmask);
-            pb.elem[k] = e;
-            pb.mesh[k] = mesh_idx;
-        }
-        pb.n += __popcll(pmask);
-    }
+    push_entry(pb, sub_list(q), q, m, meshes, push, e, mesh_idx);   // room for 64: flushed below once fuller
     const bool exact = active && st == kTopExact;
     const uint64_t xmask = ballot(exact);
     if (xmask) {
@@ -263,7 +263,7 @@ __device__ void finish_element(const MeshDev& m, int mesh_idx, int64_t e, bool a
         if (!push) *global(m.verdict + e) = v;   // listed elements: at push_flush
         if (m.min_coeff) *global(m.min_coeff + e) = bad ? __builtin_nan("") : mn;
     }
-    if (pb.n > kPushBuf - 64) push_flush(pb, q, m, meshes);
+    if (pb.n > kPushBuf - 64) push_flush(pb, sub_list(q), q, m, meshes);
 }
 
 template <bool EDGES, int G>
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(256) void k_top_f64_range(TopArgs a)
         }
         process_element<EDGES, G>(m, mi, e, e < m.n, a.q, a.max_depth, pb, BATCHED ? a.meshes : nullptr);
     }
-    push_flush(pb, a.q, a.mesh, BATCHED ? a.meshes : nullptr);
+    push_flush(pb, sub_list(a.q), a.q, a.mesh, BATCHED ? a.meshes : nullptr);
 }
 
 // LDS address space pointer, as the direct global-to-LDS loads take it.
@@ -546,7 +546,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         wait_vmem();                   // vertices and the next rows have landed
         finish_element<EDGES>(m, 0, e, active, p, false, a.q, a.max_depth, pb, nullptr);
     });
-    push_flush(pb, a.q, m, nullptr);
+    push_flush(pb, sub_list(a.q), a.q, m, nullptr);
 }
 
 // k_top_f64_range for a batch whose meshes all have trusted connectivity,
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
                         [&](const MeshDev& m, int mi, int64_t e, bool active, const V3* p) {
         finish_element<EDGES>(m, mi, e, active, p, false, a.q, a.max_depth, pb, a.meshes);
     });
-    push_flush(pb, a.q, a.mesh, a.meshes);
+    push_flush(pb, sub_list(a.q), a.q, a.mesh, a.meshes);
 }
 
 template <bool BATCHED, bool EDGES>
@@ -583,7 +583,7 @@ __global__ __launch_bounds__(256) void k_top_f64_list(TopArgs a)
         const MeshDev m = BATCHED && active ? a.meshes[mi] : a.mesh;
         process_element<EDGES, kGatherAny>(m, mi, e, active, a.q, a.max_depth, pb, BATCHED ? a.meshes : nullptr);
     }
-    push_flush(pb, a.q, a.mesh, BATCHED ? a.meshes : nullptr);
+    push_flush(pb, sub_list(a.q), a.q, a.mesh, BATCHED ? a.meshes : nullptr);
 }
 
 // FP32 filter, one element per lane: certain INVALID / VALID elements are
@@ -591,11 +591,11 @@ __global__ __launch_bounds__(256) void k_top_f64_list(TopArgs a)
 // is listed for the FP64 pass (k_top_f64_list), which decides it exactly as
 // the plain FP64 path would.
 
-// Every thread of the block calls this (block-level list reservation: one
-// atomic per block and tile instead of one per wave, which matters when
-// many elements need the FP64 pass).
+// FP32 decisions for one element per lane.  Elements that need the FP64 pass
+// go to the recheck list through the wave's buffer (as finish_element sends
+// elements to subdivision), without a block barrier per tile.
 __device__ void filter_finish(const MeshDev& m, int mesh_idx, int64_t e, bool active, const V3 p[8], bool bad,
-                              const QueueDev& q)
+                              const QueueDev& q, PushBuf& pb, const MeshDev* meshes)
 {
     int st = -1;
     float mn = 0.0f;
@@ -607,40 +607,29 @@ __device__ void filter_finish(const MeshDev& m, int mesh_idx, int64_t e, bool ac
         }
     }
     const bool recheck = active && !bad && st < 0;
-    uint8_t v = bad ? 3 : (uint8_t)st;
-    if (__syncthreads_or(recheck)) {
-        const unsigned long long slot = block_reserve(&q.cnt->n_list, recheck);
-        bool deferred = false;
-        if (recheck) {
-            if (slot < q.list_cap) {
-                q.list_elem[slot] = e;
-                q.list_mesh[slot] = mesh_idx;
-                v = kPending;
-            } else {
-                v = kDeferred;
-                deferred = true;
-            }
-        }
-        wave_count(&q.cnt->n_deferred, deferred);
-    }
-    if (active) {
+    const uint8_t v = bad ? 3 : (uint8_t)st;
+    push_entry(pb, recheck_list(q), q, m, meshes, recheck, e, mesh_idx);
+    if (active && !recheck) {
         *global(m.verdict + e) = v;
-        if (m.min_coeff && !recheck) *global(m.min_coeff + e) = bad ? __builtin_nan("") : (double)mn;
+        if (m.min_coeff) *global(m.min_coeff + e) = bad ? __builtin_nan("") : (double)mn;
     }
+    if (pb.n > kPushBuf - 64) push_flush(pb, recheck_list(q), q, m, meshes);
 }
 
 template <int G>
-__device__ void filter_element(const MeshDev& m, int mesh_idx, int64_t e, bool active, const QueueDev& q)
+__device__ void filter_element(const MeshDev& m, int mesh_idx, int64_t e, bool active, const QueueDev& q,
+                               PushBuf& pb, const MeshDev* meshes)
 {
     V3 p[8];
     bool bad = false;
     if (active) load_points_t<G>(m, e, p, bad);
-    filter_finish(m, mesh_idx, e, active, p, bad, q);
+    filter_finish(m, mesh_idx, e, active, p, bad, q, pb, meshes);
 }
 
 template <bool BATCHED, int G>
 __global__ __launch_bounds__(256) void k_filter_f32_range(TopArgs a)
 {
+    HX_PUSH_STORAGE;
     TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
     for (int64_t t = ts.next_tile(); t >= 0; t = ts.next_tile()) {
         MeshDev m;
@@ -655,8 +644,9 @@ __global__ __launch_bounds__(256) void k_filter_f32_range(TopArgs a)
             m = a.mesh;
             e = t * (int64_t)blockDim.x + threadIdx.x;
         }
-        filter_element<G>(m, mi, e, e < m.n, a.q);
+        filter_element<G>(m, mi, e, e < m.n, a.q, pb, BATCHED ? a.meshes : nullptr);
     }
+    push_flush(pb, recheck_list(a.q), a.q, a.mesh, BATCHED ? a.meshes : nullptr);
 }
 
 // k_filter_f32_range for a single mesh with trusted connectivity, through
@@ -664,14 +654,16 @@ __global__ __launch_bounds__(256) void k_filter_f32_range(TopArgs a)
 __global__ __launch_bounds__(256) void k_filter_f32_conn(TopArgs a)
 {
     __shared__ int4 stage[2 * 256];
+    HX_PUSH_STORAGE;
     const MeshDev& m = a.mesh;
     TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
     conn_prefetch_loop<8>(m.conn, m.n, ts, stage, [&](int64_t e, bool active, const int* idx) {
         V3 p[8];
         gather8(m.points, idx, p);
         wait_vmem();
-        filter_finish(m, 0, e, active, p, false, a.q);
+        filter_finish(m, 0, e, active, p, false, a.q, pb, nullptr);
     });
+    push_flush(pb, recheck_list(a.q), a.q, m, nullptr);
 }
 
 // k_filter_f32_range for a batch whose meshes all have trusted
@@ -679,11 +671,13 @@ __global__ __launch_bounds__(256) void k_filter_f32_conn(TopArgs a)
 __global__ __launch_bounds__(256) void k_filter_f32_batch_conn(TopArgs a)
 {
     __shared__ int4 stage[2 * 256];
+    HX_PUSH_STORAGE;
     TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
     batch_prefetch_loop(a.meshes, a.tile_mesh, ts, stage,
                         [&](const MeshDev& m, int mi, int64_t e, bool active, const V3* p) {
-        filter_finish(m, mi, e, active, p, false, a.q);
+        filter_finish(m, mi, e, active, p, false, a.q, pb, a.meshes);
     });
+    push_flush(pb, recheck_list(a.q), a.q, a.mesh, a.meshes);
 }
 
 // ------------------------------------------------------------ subdivision
