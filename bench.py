@@ -226,11 +226,12 @@ def batched_leg(hx, torch, synth, steps):
         st = hx.hexval_stats_t()
         st.timing = 1
         opts = hx.make_opts(precision=prec, stream=stream, stats=st)
-        hx.hexval_check_batched(descs, opts, vs, ms)      # warm-up + tuning
+        args = hx.BatchArgs(descs, vs, ms)                 # C arrays built once
+        hx.hexval_check_batched(args, opts)               # warm-up + tuning
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            hx.hexval_check_batched(descs, opts, vs, ms)
+            hx.hexval_check_batched(args, opts)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
         res[name] = {"value": total / wall, "unit": "hex/s", "ms_per_step": 1e3 * wall,

@@ -166,16 +166,28 @@ def hexval_check_ex(mesh, opts, verdicts, min_coeffs=None):
                                         _addr(verdicts), _addr(min_coeffs)))
 
 
-def hexval_check_batched(meshes, opts, verdicts, min_coeffs=None):
-    """C: hexval_check_batched (meshes: list of hexval_mesh_t; verdicts and
-    min_coeffs: lists of tensors/addresses, min_coeffs entries may be None)."""
-    n = len(meshes)
-    arr = (hexval_mesh_t * n)(*meshes)
-    v = (ctypes.c_void_p * n)(*[_addr(x) for x in verdicts])
-    m = (ctypes.c_void_p * n)(*[_addr(x) for x in min_coeffs]) if min_coeffs is not None else None
-    return _check(lib().hexval_check_batched(arr, n, ctypes.byref(opts) if opts else None,
-                                             ctypes.cast(v, ctypes.c_void_p),
-                                             ctypes.cast(m, ctypes.c_void_p) if m is not None else None))
+class BatchArgs:
+    """The C arrays of a hexval_check_batched call, built once: for a batch
+    of many meshes checked repeatedly, marshalling the lists on every call
+    costs milliseconds of host time."""
+
+    def __init__(self, meshes, verdicts, min_coeffs=None):
+        self.n = len(meshes)
+        self.meshes = (hexval_mesh_t * self.n)(*meshes)
+        self.verdicts = (ctypes.c_void_p * self.n)(*[_addr(x) for x in verdicts])
+        self.min_coeffs = ((ctypes.c_void_p * self.n)(*[_addr(x) for x in min_coeffs])
+                           if min_coeffs is not None else None)
+
+
+def hexval_check_batched(meshes, opts, verdicts=None, min_coeffs=None):
+    """C: hexval_check_batched.  meshes: a BatchArgs, or a list of
+    hexval_mesh_t with verdicts and min_coeffs as lists of tensors/addresses
+    (min_coeffs entries may be None)."""
+    a = meshes if isinstance(meshes, BatchArgs) else BatchArgs(meshes, verdicts, min_coeffs)
+    return _check(lib().hexval_check_batched(a.meshes, a.n, ctypes.byref(opts) if opts else None,
+                                             ctypes.cast(a.verdicts, ctypes.c_void_p),
+                                             ctypes.cast(a.min_coeffs, ctypes.c_void_p)
+                                             if a.min_coeffs is not None else None))
 
 
 def hexval_coefficients(mesh, stream, coeffs):

@@ -106,3 +106,16 @@ def test_binding_names_match_the_abi():
         if name == "hexval_opts_default":
             continue
         assert hasattr(hx, name), name
+
+
+def test_batch_args_marshal_once():
+    # the prepared C arrays of a batched call hold the meshes and output
+    # addresses in order (no GPU: nothing is called)
+    meshes = [hx.hexval_mesh_t(1000 + i, 10 + i, 2000 + i, 5 + i) for i in range(7)]
+    a = hx.BatchArgs(meshes, [3000 + i for i in range(7)], [4000 + i if i % 2 else 0 for i in range(7)])
+    assert a.n == 7
+    assert [a.meshes[i].n for i in range(7)] == [5 + i for i in range(7)]
+    assert [a.meshes[i].n_points for i in range(7)] == [10 + i for i in range(7)]
+    assert [a.verdicts[i] for i in range(7)] == [3000 + i for i in range(7)]
+    assert [a.min_coeffs[i] or 0 for i in range(7)] == [4000 + i if i % 2 else 0 for i in range(7)]
+    assert hx.BatchArgs(meshes, [1] * 7).min_coeffs is None
