@@ -716,13 +716,47 @@ constexpr int kNodeWords = 30;   // words of a Node that carry data
 // group copies the node into LDS (one 256-byte span), every lane takes its
 // octant's coefficients by de Casteljau at 1/2 (on the mirrored tensor
 // order) and applies the certified decisions.  Children that stay ambiguous
-// below the depth cap are appended as level L+1: a block reserves room for
-// the children of its 32 sub-boxes with one atomic.  Waves of a block move in
-// step over consecutive groups of 32 sub-boxes.
+// below the depth cap are appended as level L+1.  A block takes G groups of
+// 32 sub-boxes per step (G up to 8, fewer when the level is too small to
+// give every block G groups): it first decides every child of the G groups,
+// then reserves room for all children to append with one atomic, then
+// recomputes the appended children (from the node, still in L2) and writes
+// them.  Same-address atomics serialise at about 13 ns, so one per 32
+// sub-boxes had dominated the large levels of invalid-heavy batches.
+constexpr int kLevelGroups = 8;
+
+__device__ __forceinline__ void level_stage_node(const double* nodes, uint64_t node, int child, double* dst)
+{
+    // 8 lanes x 32 bytes: the whole node (words 30, 31 are padding)
+    const double2* src = reinterpret_cast<const double2*>(nodes + node * 32 + 4 * child);
+    const double2 w0 = src[0], w1 = src[1];
+    dst += 4 * child;
+    dst[0] = w0.x;
+    dst[1] = w0.y;
+    if (child < 7) {
+        dst[2] = w1.x;
+        dst[3] = w1.y;
+    }
+}
+
+// The lane's child octant of the staged node: its 27 coefficients in t, and
+// the node's scale, element slot and orientation pattern.
+__device__ __forceinline__ void level_child(const double* nd, int child, double t[27], double& scale,
+                                            int64_t& sslot)
+{
+    const uint64_t lo = __double_as_longlong(nd[29]);
+    const int pat = (int)(lo >> 32) ^ child;
+    sslot = (int64_t)__double_as_longlong(nd[28]);
+    scale = nd[27];
+#pragma unroll
+    for (int k = 0; k < 27; ++k) t[k] = nd[mirrored(k, pat)];
+    lower_octant(t);
+}
+
 __global__ __launch_bounds__(256) void k_level(LevelArgs a)
 {
     __shared__ double stage_mem[4][8][kNodeWords];
-    __shared__ unsigned int wave_push[4];
+    __shared__ unsigned int wave_push[kLevelGroups][4];
     __shared__ unsigned long long block_base;
     const int wid = threadIdx.x >> 6;
     double (*stage)[kNodeWords] = stage_mem[wid];
@@ -735,84 +769,94 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a)
     const LevelRange r = level_range(cnt, a.level, cap);
     const int level = a.level + 1;   // level of the children evaluated here
     const double* nodes = reinterpret_cast<const double*>(q.nodes);
-    for (uint64_t b0 = (uint64_t)blockIdx.x * 32; b0 < r.count; b0 += (uint64_t)gridDim.x * 32) {
-        const uint64_t i = b0 + (uint64_t)(wid * 8 + grp);
-        const bool act = i < r.count;
-        if (act) {
-            // 8 lanes x 32 bytes: the whole node (words 30, 31 are padding)
-            const double2* src = reinterpret_cast<const double2*>(nodes + (r.base + i) * 32 + 4 * child);
-            const double2 w0 = src[0], w1 = src[1];
-            double* dst = stage[grp] + 4 * child;
-            dst[0] = w0.x;
-            dst[1] = w0.y;
-            if (child < 7) {
-                dst[2] = w1.x;
-                dst[3] = w1.y;
-            }
-        }
-        lds_order();
-        bool push = false, invalid = false, undecided = false, inexact = false;
-        double t[27];
-        int64_t sslot = 0;
-        double scale = 0.0;
-        if (act) {
-            const double* nd = stage[grp];
-            const uint64_t lo = __double_as_longlong(nd[29]);
-            const int pat = (int)(lo >> 32) ^ child;
-            sslot = (int64_t)__double_as_longlong(nd[28]);
-            scale = nd[27];
+    // groups per step: as many as keep every block busy, at most kLevelGroups
+    const uint64_t groups = (r.count + 31) / 32;
+    const uint64_t per_block = groups / gridDim.x;
+    const int G = per_block >= (uint64_t)kLevelGroups ? kLevelGroups : per_block < 1 ? 1 : (int)per_block;
+    const uint64_t span = 32ull * (uint64_t)G;
+    for (uint64_t b0 = (uint64_t)blockIdx.x * span; b0 < r.count; b0 += (uint64_t)gridDim.x * span) {
+        // decide every child of the G groups
+        uint32_t pushed = 0;   // bit g: this lane's child of group g is appended
+        for (int g = 0; g < G; ++g) {
+            const uint64_t i = b0 + (uint64_t)(32 * g + wid * 8 + grp);
+            const bool act = i < r.count;
+            if (act) level_stage_node(nodes, r.base + i, child, stage[grp]);
+            lds_order();
+            bool push = false, invalid = false, undecided = false, inexact = false;
+            int64_t sslot = 0;
+            if (act) {
+                double t[27];
+                double scale;
+                level_child(stage[grp], child, t, scale, sslot);
+                const bool dead = (__hip_atomic_load(q.sub_flags + sslot, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT) & kFlagInvalid) != 0u;
+                if (!dead) {
+                    const double tau = level_threshold(scale, level);
+                    const double m8 = fmin(fmin(fmin(t[0], t[2]), fmin(t[6], t[8])),
+                                           fmin(fmin(t[18], t[20]), fmin(t[24], t[26])));
+                    double m19 = t[1];
 #pragma unroll
-            for (int k = 0; k < 27; ++k) t[k] = nd[mirrored(k, pat)];
-            const bool dead = (__hip_atomic_load(q.sub_flags + sslot, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT) & kFlagInvalid) != 0u;
-            if (!dead) {
-                lower_octant(t);
-                const double tau = level_threshold(scale, level);
-                const double m8 = fmin(fmin(fmin(t[0], t[2]), fmin(t[6], t[8])),
-                                       fmin(fmin(t[18], t[20]), fmin(t[24], t[26])));
-                double m19 = t[1];
-#pragma unroll
-                for (int k = 3; k < 26; ++k)
-                    if (k != 6 && k != 8 && k != 18 && k != 20 && k != 24) m19 = fmin(m19, t[k]);
-                if (m8 <= -tau) invalid = true;
-                else if (!(m8 > tau)) inexact = true;
-                else if (m19 > tau) { /* positive on this sub-box */ }
-                else if (level < a.max_depth) push = true;
-                else if (m19 <= -tau) undecided = true;
-                else inexact = true;
-            }
-        }
-        uint32_t fl = (invalid ? kFlagInvalid : 0u) | (undecided ? kFlagUndecided : 0u) |
-                      (inexact ? kFlagExact : 0u);
-        // room for the children that stay ambiguous: one atomic per block
-        const uint64_t pmask = ballot(push);
-        if (lane == 0) wave_push[wid] = (unsigned int)__popcll(pmask);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const unsigned int total = wave_push[0] + wave_push[1] + wave_push[2] + wave_push[3];
-            block_base = total ? atomicAdd(&cnt->lvl[level], (unsigned long long)total) : 0ull;
-        }
-        __syncthreads();
-        if (pmask) {
-            unsigned long long off = block_base + (unsigned long long)lane_rank(pmask);
-            for (int w = 0; w < wid; ++w) off += wave_push[w];
-            const uint64_t ns = r.next_base + off;
-            if (push) {
-                if (ns < cap) {
-                    double* out = reinterpret_cast<double*>(q.nodes + ns);
-#pragma unroll
-                    for (int k = 0; k < 27; ++k) out[k] = t[k];
-                    out[27] = scale;
-                    out[28] = __longlong_as_double(sslot);
-                    out[29] = __longlong_as_double((long long)((uint64_t)(uint32_t)level |
-                                                               ((uint64_t)(uint32_t)child << 32)));
-                } else {
-                    fl |= kFlagOverflow;
+                    for (int k = 3; k < 26; ++k)
+                        if (k != 6 && k != 8 && k != 18 && k != 20 && k != 24) m19 = fmin(m19, t[k]);
+                    if (m8 <= -tau) invalid = true;
+                    else if (!(m8 > tau)) inexact = true;
+                    else if (m19 > tau) { /* positive on this sub-box */ }
+                    else if (level < a.max_depth) push = true;
+                    else if (m19 <= -tau) undecided = true;
+                    else inexact = true;
                 }
             }
+            const uint32_t fl = (invalid ? kFlagInvalid : 0u) | (undecided ? kFlagUndecided : 0u) |
+                                (inexact ? kFlagExact : 0u);
+            if (fl) atomicOr(q.sub_flags + sslot, fl);
+            const uint64_t pmask = ballot(push);
+            if (lane == 0) wave_push[g][wid] = (unsigned int)__popcll(pmask);
+            if (push) pushed |= 1u << g;
+            lds_order();               // the node is read before the next one is staged
         }
-        if (fl) atomicOr(q.sub_flags + sslot, fl);
-        __syncthreads();   // wave_push and block_base are rewritten next round
+        // room for every appended child of the step: one atomic per block
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long total = 0;
+            for (int g = 0; g < G; ++g)
+                total += wave_push[g][0] + wave_push[g][1] + wave_push[g][2] + wave_push[g][3];
+            block_base = total ? atomicAdd(&cnt->lvl[level], total) : 0ull;
+        }
+        __syncthreads();
+        // write the appended children, in order of groups, waves and lanes
+        unsigned long long off = block_base;
+        for (int g = 0; g < G; ++g) {
+            const bool push = (pushed >> g) & 1u;
+            const uint64_t pmask = ballot(push);
+            if (pmask) {
+                const uint64_t i = b0 + (uint64_t)(32 * g + wid * 8 + grp);
+                if (i < r.count) level_stage_node(nodes, r.base + i, child, stage[grp]);
+                lds_order();
+                if (push) {
+                    double t[27];
+                    double scale;
+                    int64_t sslot;
+                    level_child(stage[grp], child, t, scale, sslot);
+                    unsigned long long o = off + (unsigned long long)lane_rank(pmask);
+                    for (int w = 0; w < wid; ++w) o += wave_push[g][w];
+                    const uint64_t ns = r.next_base + o;
+                    if (ns < cap) {
+                        double* out = reinterpret_cast<double*>(q.nodes + ns);
+#pragma unroll
+                        for (int k = 0; k < 27; ++k) out[k] = t[k];
+                        out[27] = scale;
+                        out[28] = __longlong_as_double(sslot);
+                        out[29] = __longlong_as_double((long long)((uint64_t)(uint32_t)level |
+                                                                   ((uint64_t)(uint32_t)child << 32)));
+                    } else {
+                        atomicOr(q.sub_flags + sslot, kFlagOverflow);
+                    }
+                }
+                lds_order();
+            }
+            off += wave_push[g][0] + wave_push[g][1] + wave_push[g][2] + wave_push[g][3];
+        }
+        __syncthreads();   // wave_push and block_base are rewritten next step
     }
 }
 
