@@ -227,3 +227,18 @@ def test_fp32_filter_small_list_defers_to_fp64_rounds():
     # FP32 filter with a 64-node subdivision queue: deferred FP64 passes
     v, m, st = _run(torch, P, precision=hx.FP32_FILTER, queue_capacity=64)
     assert_parity(v, None, P, label="fp32 rounds")
+
+
+def test_fp32_filter_full_recheck_list_defers_to_rounds():
+    # 300,000 near-degenerate hexes all need the FP64 recheck, far more than
+    # the recheck list holds (2^16 entries here): the entries past it are
+    # deferred and checked in later rounds, with the verdicts of plain FP64
+    torch = torch_cuda()
+    P = synth.near_degenerate_hexes(300000, seed=17)
+    v32, _, st = _run(torch, P, precision=hx.FP32_FILTER)
+    v64, _, _ = _run(torch, P, precision=hx.FP64)
+    print(f"stats {st}", flush=True)
+    assert st["n_rounds"] > 1
+    assert np.array_equal(v32, v64)
+    idx = np.arange(0, P.shape[0], 15)
+    assert_parity(v32[idx], None, P[idx], label="fp32 list rounds")
