@@ -174,15 +174,25 @@ static void worker_loop(hexval_server* sv, Slot* sl)
                 }
             }
         }
-        const int st = batch.size() == 1 ? run_one(sv, *sl, *batch[0]) : run_batch(sv, *sl, batch);
-        const std::string err = st ? last_error() : "";
+        std::vector<int> status(batch.size(), HEXVAL_OK);
+        std::vector<std::string> error(batch.size());
+        bool alone = batch.size() == 1;
+        if (!alone && run_batch(sv, *sl, batch) != HEXVAL_OK)
+            alone = true;   // one bad request must not fail the others: run each by itself
+        if (alone) {
+            for (size_t k = 0; k < batch.size(); ++k) {
+                status[k] = run_one(sv, *sl, *batch[k]);
+                if (status[k]) error[k] = last_error();
+            }
+        }
         {
             std::lock_guard<std::mutex> lk(sv->mu);
             const auto now = Clock::now();
-            for (ServerRequest* rq : batch) {
+            for (size_t k = 0; k < batch.size(); ++k) {
+                ServerRequest* rq = batch[k];
                 sv->in_use -= (int64_t)rq->upload_bytes;
-                rq->status = st;
-                rq->error = err;
+                rq->status = status[k];
+                rq->error = error[k];
                 rq->t_done = now;
                 rq->done = true;
             }

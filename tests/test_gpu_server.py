@@ -113,3 +113,31 @@ def test_server_host_upload_and_budget():
         assert e.value.status == hx.E_BUSY
     finally:
         hx.hexval_server_destroy(sv)
+
+
+def test_server_bad_request_does_not_fail_its_batch():
+    # with index validation on, a device-resident request that gives no
+    # vertex count passes submission but is refused when run; queued with
+    # good requests that arrive at the same time, only it reports the error
+    torch = torch_cuda()
+    meshes = _pool(torch, 6, seed=9, lo=3.0, hi=4.5)
+    alone = [hx.check(V, C, validate_indices=True)[0] for V, C in meshes]
+    torch.cuda.synchronize()
+    tmpl = _templates(meshes)
+    tmpl[3].mesh.n_points = 0
+    sv = hx.hexval_server_create(hx.make_opts(validate_indices=True), 8 << 30, 1)
+    try:
+        idx = np.arange(12) % 6
+        sizes = [meshes[i][1].shape[0] for i in idx]
+        arena = torch.empty(loadgen.arena_bytes(sizes), dtype=torch.uint8, device="cuda")
+        _, st, off, _ = loadgen.run(sv, np.zeros(12), idx, tmpl, arena)
+        torch.cuda.synchronize()
+        for k, i in enumerate(idx):
+            if i == 3:
+                assert st[k] == hx.E_ARG, k
+            else:
+                assert st[k] == hx.OK, k
+                v, _ = _outputs(torch, arena, int(off[k]), sizes[k])
+                assert torch.equal(v, alone[i]), k
+    finally:
+        hx.hexval_server_destroy(sv)
