@@ -62,7 +62,7 @@ enum {
     HEXVAL_E_ARG = 1,   /* invalid argument (see conventions) */
     HEXVAL_E_HIP = 2,   /* HIP runtime error, no usable gfx950 device, or kernel failure */
     HEXVAL_E_NOMEM = 3, /* device or host allocation failed */
-    HEXVAL_E_QUEUE = 4, /* the subdivision queue could not make progress */
+    HEXVAL_E_QUEUE = 4, /* the subdivision queue cannot hold one element's tree */
     HEXVAL_E_BUSY = 5   /* server: no capacity for this request (never returned by submit) */
 };
 
@@ -114,7 +114,9 @@ typedef struct {
                                  give BAD_INPUT (default 0: indices are trusted) */
     int32_t block_threads;    /* first-pass block size: 0 = tuned, else 64..256,
                                  a multiple of 64 */
-    int64_t queue_capacity;   /* subdivision queue nodes, 0 = automatic */
+    int64_t queue_capacity;   /* subdivision queue nodes, 0 = automatic.  Elements
+                                 that do not fit are checked in later rounds,
+                                 fewer at a time when a round completes none */
     int64_t grid_blocks;      /* first-pass grid: 0 = tuned, else blocks (rounded up
                                  to a multiple of 8) */
     void* stream;             /* hipStream_t to run on; NULL = the null stream */

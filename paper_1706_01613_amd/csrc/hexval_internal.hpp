@@ -64,6 +64,7 @@ struct alignas(256) Counters {
 struct QueueDev {
     Node* nodes;
     uint64_t node_cap;
+    uint64_t root_cap;     // subdivided elements a round may list (<= node_cap)
     int64_t* sub_elem;     // [node_cap] element id of subdivided slot
     int32_t* sub_mesh;     // [node_cap] mesh index
     uint32_t* sub_flags;   // [node_cap]

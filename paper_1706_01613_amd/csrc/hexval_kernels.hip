@@ -166,7 +166,7 @@ struct ListRef {
     uint64_t cap;
 };
 
-__device__ __forceinline__ ListRef sub_list(const QueueDev& q) { return {&q.cnt->n_sub, q.sub_elem, q.sub_mesh, q.node_cap}; }
+__device__ __forceinline__ ListRef sub_list(const QueueDev& q) { return {&q.cnt->n_sub, q.sub_elem, q.sub_mesh, q.root_cap}; }
 __device__ __forceinline__ ListRef recheck_list(const QueueDev& q)
 {
     return {&q.cnt->n_list, q.list_elem, q.list_mesh, q.list_cap};
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(256) void k_roots(RootArgs a)
 {
     const QueueDev& q = a.q;
     const unsigned long long ns = q.cnt->n_sub;
-    const int64_t n = (int64_t)(ns < q.node_cap ? ns : q.node_cap);
+    const int64_t n = (int64_t)(ns < q.root_cap ? ns : q.root_cap);
     if (blockIdx.x == 0 && threadIdx.x == 0) q.cnt->lvl[0] = (unsigned long long)n;
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
          s += (int64_t)gridDim.x * blockDim.x) {
@@ -864,7 +864,7 @@ __global__ __launch_bounds__(256) void k_fold(FoldArgs a)
 {
     const QueueDev& q = a.q;
     const unsigned long long ns = *(&q.cnt->n_sub);
-    const int64_t n = (int64_t)(ns < q.node_cap ? ns : q.node_cap);
+    const int64_t n = (int64_t)(ns < q.root_cap ? ns : q.root_cap);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     // whole waves iterate together (wave-level list appends and counters)
     for (int64_t s0 = blockIdx.x * (int64_t)blockDim.x; s0 < n; s0 += stride) {

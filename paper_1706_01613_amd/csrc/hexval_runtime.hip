@@ -246,6 +246,7 @@ QueueDev Workspace::queue() const
     QueueDev q;
     q.nodes = nodes;
     q.node_cap = node_cap;
+    q.root_cap = node_cap;
     q.sub_elem = sub_elem;
     q.sub_mesh = sub_mesh;
     q.sub_flags = sub_flags;
@@ -536,6 +537,7 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     QueueDev q = w.queue();
     // a pooled workspace may be larger than this call asked for
     if (node_cap) q.node_cap = std::min<uint64_t>(q.node_cap, node_cap);
+    q.root_cap = q.node_cap;
     if (list_cap) q.list_cap = std::min<uint64_t>(q.list_cap, list_cap);
 
     MeshDev single{};
@@ -676,7 +678,7 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         HX_HIP(hipStreamSynchronize(s));
         const Counters c = *w.hcnt;
         if (st) {
-            st->n_subdivided += (int64_t)std::min<uint64_t>(c.n_sub, q.node_cap);
+            st->n_subdivided += (int64_t)std::min<uint64_t>(c.n_sub, q.root_cap);
             // children evaluated: 8 per stored sub-box of levels 0..max_depth-1
             uint64_t base = 0;
             for (int L = 0; L < o.max_depth && c.n_sub > 0; ++L) {
@@ -723,9 +725,14 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
             remaining = c.n_deferred;
         } else {
             const uint64_t listed = std::min<uint64_t>(prev_remaining, q.list_cap);
-            if (c.n_deferred >= listed)
-                return fail(HEXVAL_E_QUEUE, "subdivision queue of %llu nodes too small to make progress",
-                            (unsigned long long)q.node_cap);
+            if (c.n_deferred >= listed) {
+                // nothing completed: the listed elements' trees crowded each
+                // other out; list fewer per round, down to one at a time
+                if (q.root_cap <= 1)
+                    return fail(HEXVAL_E_QUEUE, "subdivision queue of %llu nodes too small to make progress",
+                                (unsigned long long)q.node_cap);
+                q.root_cap = std::max<uint64_t>(1, q.root_cap / 8);
+            }
             remaining = prev_remaining - listed + c.n_deferred;
         }
         if (remaining == 0) break;
@@ -772,6 +779,7 @@ int run_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts_in, do
     if ((rc = w.ensure(node_cap, 0, 1, 1))) return rc;
     QueueDev q = w.queue();
     q.node_cap = std::min<uint64_t>(q.node_cap, node_cap);
+    q.root_cap = q.node_cap;
     if ((rc = w.ensure_minj(q.node_cap, (uint64_t)n))) return rc;
 
     MinjArgs a{};

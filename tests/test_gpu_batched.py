@@ -121,3 +121,22 @@ def test_config4_full_size_batched():
         V, C = meshes[k]
         _say(f"config 4: oracle on mesh {k} ({C.shape[0]} hexes)")
         assert_parity(vs[k].cpu().numpy(), None, V.cpu().numpy(), C.cpu().numpy(), label=f"mesh {k}")
+
+
+@pytest.mark.parametrize("precision", [hx.FP64, hx.FP32_FILTER])
+def test_batched_tiny_queue_rounds_equal_alone(precision):
+    # a 64-node subdivision queue: most listed elements of the batch are
+    # deferred when their wave's buffer is appended and checked in later
+    # rounds; every mesh still gets the verdicts of checking it alone
+    # (lattices jittered like the single-mesh tiny-queue case, whose trees
+    # stay shallow enough for such a queue to make progress)
+    torch = torch_cuda()
+    dims = [(20 + k % 7, 18 + k % 5, 10 + k % 9) for k in range(12)]
+    meshes = [synth.warped_lattice_torch(nx, ny, nz, jitter=0.45, seed=40 + k) for k, (nx, ny, nz) in enumerate(dims)]
+    st = hx.hexval_stats_t()
+    vs, ms = _batched(torch, meshes, precision, stats=st, queue_capacity=64)
+    _say(f"tiny queue batch: {st.as_dict()}")
+    assert st.n_rounds > 1
+    for k, ((V, C), v) in enumerate(zip(meshes, vs)):
+        va, _ = _alone(torch, V, C, precision=precision)
+        assert torch.equal(v, va), k
