@@ -989,12 +989,14 @@ __device__ void minj_element(const MinjArgs& a, int64_t e, bool active, const V3
         if (bad) {
             st = kMjBadInput;
         } else {
+            // before the arithmetic, so that the corners need not stay live
+            // through it
+            bool finite = true;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                finite = finite && isfinite(p[k].x) && isfinite(p[k].y) && isfinite(p[k].z);
             const LeanResult r = element_lean(p, false);
             if (!r.certified_range) {
-                bool finite = true;
-#pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    finite = finite && isfinite(p[k].x) && isfinite(p[k].y) && isfinite(p[k].z);
                 st = finite ? kMjOutOfRange : kMjBadInput;
             } else {
                 lo = r.min27;
