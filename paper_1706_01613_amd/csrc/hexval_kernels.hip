@@ -1099,10 +1099,26 @@ __global__ __launch_bounds__(256) void k_minj_roots(MinjArgs a)
 // level L+1 (one atomic per block of 32 boxes) and every lane writes its
 // child, with the child's minimum coefficient in word 30.  A box whose
 // children do not fit is retired and its element flagged.
+__device__ __forceinline__ void minj_stage_node(const double* nodes, uint64_t node, int child, double* dst)
+{
+    const double2* src = reinterpret_cast<const double2*>(nodes + node * 32 + 4 * child);
+    const double2 w0 = src[0], w1 = src[1];
+    dst += 4 * child;
+    dst[0] = w0.x;
+    dst[1] = w0.y;
+    dst[2] = w1.x;
+    dst[3] = w1.y;
+}
+
+// One level of the min J refinement: eight lanes per stored box.  A box whose
+// bounds are not yet within the tolerance is split into its 8 octants (all
+// stored, 8 slots).  As in k_level, a block decides G groups of 32 boxes,
+// reserves the slots of all their split boxes with one atomic, then writes
+// the octants.
 __global__ __launch_bounds__(256) void k_minj_level(MinjArgs a)
 {
     __shared__ double stage_mem[4][8][32];
-    __shared__ unsigned int wave_split[4];
+    __shared__ unsigned int wave_split[kLevelGroups][4];
     __shared__ unsigned long long block_base;
     const int wid = threadIdx.x >> 6;
     double (*stage)[32] = stage_mem[wid];
@@ -1126,85 +1142,115 @@ __global__ __launch_bounds__(256) void k_minj_level(MinjArgs a)
     }
     const LevelRange r = minj_level_range(cnt, L, cap);
     const double* nodes = reinterpret_cast<const double*>(q.nodes);
-    for (uint64_t b0 = (uint64_t)blockIdx.x * 32; b0 < r.count; b0 += (uint64_t)gridDim.x * 32) {
-        const uint64_t i = b0 + (uint64_t)(wid * 8 + grp);
-        const bool act = i < r.count;
-        if (act) {
-            const double2* src = reinterpret_cast<const double2*>(nodes + (r.base + i) * 32 + 4 * child);
-            const double2 w0 = src[0], w1 = src[1];
-            double* dst = stage[grp] + 4 * child;
-            dst[0] = w0.x;
-            dst[1] = w0.y;
-            dst[2] = w1.x;
-            dst[3] = w1.y;
+    const uint64_t groups = (r.count + 31) / 32;
+    const uint64_t per_block = groups / gridDim.x;
+    const int G = per_block >= (uint64_t)kLevelGroups ? kLevelGroups : per_block < 1 ? 1 : (int)per_block;
+    const uint64_t span = 32ull * (uint64_t)G;
+    // the box of the lane's group: bounds and the decision
+    struct Box {
+        double lo, scale, U;
+        int64_t sslot;
+        int orient;
+        bool split, capped;
+    };
+    auto decide = [&](const double* nd) {
+        Box x;
+        x.lo = nd[30];
+        x.scale = nd[27];
+        x.sslot = (int64_t)__double_as_longlong(nd[28]);
+        x.orient = (int)((uint64_t)__double_as_longlong(nd[29]) >> 32);
+        x.U = of_ord(R[x.sslot]);
+        const bool close = x.lo >= x.U - a.mj.rtol * x.scale / 6.0;
+        x.split = L == 0 || (!close && L < a.max_depth);
+        x.capped = !x.split && !close;
+        return x;
+    };
+    for (uint64_t b0 = (uint64_t)blockIdx.x * span; b0 < r.count; b0 += (uint64_t)gridDim.x * span) {
+        // decide the boxes of the G groups; boxes not split are final here
+        uint32_t splits = 0;   // bit g: the lane's box of group g is split
+        for (int g = 0; g < G; ++g) {
+            const uint64_t i = b0 + (uint64_t)(32 * g + wid * 8 + grp);
+            const bool act = i < r.count;
+            if (act) minj_stage_node(nodes, r.base + i, child, stage[grp]);
+            lds_order();
+            bool split = false;
+            if (act) {
+                const Box x = decide(stage[grp]);
+                split = x.split;
+                if (!split && child == 0) {
+                    atomicMin(&a.mj.lb[x.sslot], ord_of(x.lo));
+                    if (x.capped) atomicOr(q.sub_flags + x.sslot, kFlagUndecided);
+                }
+            }
+            const uint64_t smask = ballot(split && child == 0);
+            if (lane == 0) wave_split[g][wid] = (unsigned int)__popcll(smask);
+            if (split) splits |= 1u << g;
+            lds_order();               // the box is read before the next one is staged
         }
-        lds_order();
-        bool split = false, capped = false;
-        double lo = 0.0, scale = 0.0, U = 0.0;
-        int64_t sslot = 0;
-        int orient = 0;
-        if (act) {
-            const double* nd = stage[grp];
-            lo = nd[30];
-            scale = nd[27];
-            sslot = (int64_t)__double_as_longlong(nd[28]);
-            orient = (int)((uint64_t)__double_as_longlong(nd[29]) >> 32);
-            U = of_ord(R[sslot]);
-            const bool close = lo >= U - a.mj.rtol * scale / 6.0;
-            split = L == 0 || (!close && L < a.max_depth);
-            capped = !split && !close;
-        }
-        // 8 slots per split box, reserved for the whole block at once
-        const uint64_t smask = ballot(split && child == 0);
-        if (lane == 0) wave_split[wid] = (unsigned int)__popcll(smask);
+        // 8 slots per split box, for the whole step at once
         __syncthreads();
         if (threadIdx.x == 0) {
-            const unsigned int total = wave_split[0] + wave_split[1] + wave_split[2] + wave_split[3];
+            unsigned long long total = 0;
+            for (int g = 0; g < G; ++g)
+                total += wave_split[g][0] + wave_split[g][1] + wave_split[g][2] + wave_split[g][3];
             block_base = total ? atomicAdd(&cnt->lvl[L + 1], 8ull * total) : 0ull;
         }
         __syncthreads();
-        bool stored = false;
-        uint64_t first = 0;
-        if (split) {
-            unsigned long long rank = (unsigned long long)__popcll(smask & ((1ull << (grp * 8)) - 1ull));
-            for (int w = 0; w < wid; ++w) rank += wave_split[w];
-            first = r.next_base + block_base + 8ull * rank;
-            stored = first + 8 <= cap;
-        }
-        double cmin = HUGE_VAL;
-        if (stored) {
-            double t[27];
-            const double* nd = stage[grp];
-            const int pat = orient ^ child;
+        unsigned long long before = 0;   // split boxes of the step's earlier groups
+        for (int g = 0; g < G; ++g) {
+            const bool split = (splits >> g) & 1u;
+            const uint64_t smask = ballot(split && child == 0);
+            if (smask) {
+                const uint64_t i = b0 + (uint64_t)(32 * g + wid * 8 + grp);
+                if (i < r.count) minj_stage_node(nodes, r.base + i, child, stage[grp]);
+                lds_order();
+                double cmin = HUGE_VAL;
+                bool stored = false;
+                Box x{};
+                if (split) {
+                    x = decide(stage[grp]);
+                    unsigned long long rank = before + (unsigned long long)__popcll(smask & ((1ull << (grp * 8)) - 1ull));
+                    for (int w = 0; w < wid; ++w) rank += wave_split[g][w];
+                    const uint64_t first = r.next_base + block_base + 8ull * rank;
+                    stored = first + 8 <= cap;
+                    if (stored) {
+                        double t[27];
+                        const double* nd = stage[grp];
+                        const int pat = x.orient ^ child;
 #pragma unroll
-            for (int k = 0; k < 27; ++k) t[k] = nd[mirrored(k, pat)];
-            lower_octant(t);
-            cmin = fmin(fmin(fmin(t[0], t[2]), fmin(t[6], t[8])), fmin(fmin(t[18], t[20]), fmin(t[24], t[26])));
-            double m27 = t[0];
+                        for (int k = 0; k < 27; ++k) t[k] = nd[mirrored(k, pat)];
+                        lower_octant(t);
+                        cmin = fmin(fmin(fmin(t[0], t[2]), fmin(t[6], t[8])),
+                                    fmin(fmin(t[18], t[20]), fmin(t[24], t[26])));
+                        double m27 = t[0];
 #pragma unroll
-            for (int k = 1; k < 27; ++k) m27 = fmin(m27, t[k]);
-            double* out = reinterpret_cast<double*>(q.nodes + first + child);
+                        for (int k = 1; k < 27; ++k) m27 = fmin(m27, t[k]);
+                        double* out = reinterpret_cast<double*>(q.nodes + first + child);
 #pragma unroll
-            for (int k = 0; k < 27; ++k) out[k] = t[k];
-            out[27] = scale;
-            out[28] = __longlong_as_double(sslot);
-            out[29] = __longlong_as_double((long long)((uint64_t)(uint32_t)(L + 1) |
-                                                       ((uint64_t)(uint32_t)child << 32)));
-            out[30] = m27;
-        }
+                        for (int k = 0; k < 27; ++k) out[k] = t[k];
+                        out[27] = x.scale;
+                        out[28] = __longlong_as_double(x.sslot);
+                        out[29] = __longlong_as_double((long long)((uint64_t)(uint32_t)(L + 1) |
+                                                                   ((uint64_t)(uint32_t)child << 32)));
+                        out[30] = m27;
+                    }
+                }
 #pragma unroll
-        for (int d = 1; d < 8; d <<= 1) cmin = fmin(cmin, __shfl_xor(cmin, d, 64));
-        if (act && child == 0) {
-            if (stored) {
-                atomicMin(&W[sslot], ord_of(fmin(U, cmin)));
-                atomicMin(&a.mj.ufinal[sslot], ord_of(cmin));
-            } else {
-                atomicMin(&a.mj.lb[sslot], ord_of(lo));
-                const uint32_t fl = (capped ? kFlagUndecided : 0u) | (split ? kFlagOverflow : 0u);
-                if (fl) atomicOr(q.sub_flags + sslot, fl);
+                for (int d = 1; d < 8; d <<= 1) cmin = fmin(cmin, __shfl_xor(cmin, d, 64));
+                if (split && child == 0) {
+                    if (stored) {
+                        atomicMin(&W[x.sslot], ord_of(fmin(x.U, cmin)));
+                        atomicMin(&a.mj.ufinal[x.sslot], ord_of(cmin));
+                    } else {
+                        atomicMin(&a.mj.lb[x.sslot], ord_of(x.lo));
+                        atomicOr(q.sub_flags + x.sslot, kFlagOverflow);
+                    }
+                }
+                lds_order();
             }
+            before += wave_split[g][0] + wave_split[g][1] + wave_split[g][2] + wave_split[g][3];
         }
-        __syncthreads();   // wave_split and block_base are rewritten next round
+        __syncthreads();   // wave_split and block_base are rewritten next step
     }
 }
 
