@@ -722,7 +722,9 @@ constexpr int kNodeWords = 30;   // words of a Node that carry data
 // then reserves room for all children to append with one atomic, then
 // recomputes the appended children (from the node, still in L2) and writes
 // them.  Same-address atomics serialise at about 13 ns, so one per 32
-// sub-boxes had dominated the large levels of invalid-heavy batches.
+// sub-boxes had dominated the large levels of invalid-heavy batches.  With
+// one group per step (small levels) the children stay in registers across
+// the reservation instead.
 constexpr int kLevelGroups = 8;
 
 __device__ __forceinline__ void level_stage_node(const double* nodes, uint64_t node, int child, double* dst)
@@ -753,6 +755,47 @@ __device__ __forceinline__ void level_child(const double* nd, int child, double 
     lower_octant(t);
 }
 
+// The certified decisions of Section 6 for one child sub-box of the given
+// level (tau: the rounding-error bound at that level).
+enum LevelDecision : int { kChildDone = 0, kChildPush, kChildInvalid, kChildUndecided, kChildInexact };
+
+__device__ __forceinline__ int level_decide(const double t[27], double scale, int level, int max_depth)
+{
+    const double tau = level_threshold(scale, level);
+    const double m8 = fmin(fmin(fmin(t[0], t[2]), fmin(t[6], t[8])),
+                           fmin(fmin(t[18], t[20]), fmin(t[24], t[26])));
+    double m19 = t[1];
+#pragma unroll
+    for (int k = 3; k < 26; ++k)
+        if (k != 6 && k != 8 && k != 18 && k != 20 && k != 24) m19 = fmin(m19, t[k]);
+    if (m8 <= -tau) return kChildInvalid;
+    if (!(m8 > tau)) return kChildInexact;
+    if (m19 > tau) return kChildDone;          // positive on this sub-box
+    if (level < max_depth) return kChildPush;
+    if (m19 <= -tau) return kChildUndecided;
+    return kChildInexact;
+}
+
+__device__ __forceinline__ uint32_t level_flags(int d)
+{
+    return d == kChildInvalid ? kFlagInvalid : d == kChildUndecided ? kFlagUndecided
+                                             : d == kChildInexact ? kFlagExact : 0u;
+}
+
+// Stores an appended child at slot ns; false when the store is full.
+__device__ __forceinline__ bool level_write(const QueueDev& q, uint64_t ns, const double t[27], double scale,
+                                            int64_t sslot, int level, int child)
+{
+    if (ns >= q.node_cap) return false;
+    double* out = reinterpret_cast<double*>(q.nodes + ns);
+#pragma unroll
+    for (int k = 0; k < 27; ++k) out[k] = t[k];
+    out[27] = scale;
+    out[28] = __longlong_as_double(sslot);
+    out[29] = __longlong_as_double((long long)((uint64_t)(uint32_t)level | ((uint64_t)(uint32_t)child << 32)));
+    return true;
+}
+
 __global__ __launch_bounds__(256) void k_level(LevelArgs a)
 {
     __shared__ double stage_mem[4][8][kNodeWords];
@@ -774,6 +817,44 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a)
     const uint64_t per_block = groups / gridDim.x;
     const int G = per_block >= (uint64_t)kLevelGroups ? kLevelGroups : per_block < 1 ? 1 : (int)per_block;
     const uint64_t span = 32ull * (uint64_t)G;
+    if (G == 1) {
+        for (uint64_t b0 = (uint64_t)blockIdx.x * 32; b0 < r.count; b0 += (uint64_t)gridDim.x * 32) {
+            // one group per step (small levels): decide, reserve and write
+            // with the children still in registers
+            const uint64_t i = b0 + (uint64_t)(wid * 8 + grp);
+            const bool act = i < r.count;
+            if (act) level_stage_node(nodes, r.base + i, child, stage[grp]);
+            lds_order();
+            int d = kChildDone;
+            int64_t sslot = 0;
+            double scale = 0.0;
+            double t[27];
+            if (act) {
+                level_child(stage[grp], child, t, scale, sslot);
+                const bool dead = (__hip_atomic_load(q.sub_flags + sslot, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT) & kFlagInvalid) != 0u;
+                if (!dead) d = level_decide(t, scale, level, a.max_depth);
+            }
+            const bool push = d == kChildPush;
+            uint32_t fl = level_flags(d);
+            const uint64_t pmask = ballot(push);
+            if (lane == 0) wave_push[0][wid] = (unsigned int)__popcll(pmask);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const unsigned long long total = wave_push[0][0] + wave_push[0][1] + wave_push[0][2] + wave_push[0][3];
+                block_base = total ? atomicAdd(&cnt->lvl[level], total) : 0ull;
+            }
+            __syncthreads();
+            if (push) {
+                unsigned long long o = block_base + (unsigned long long)lane_rank(pmask);
+                for (int w = 0; w < wid; ++w) o += wave_push[0][w];
+                if (!level_write(q, r.next_base + o, t, scale, sslot, level, child)) fl |= kFlagOverflow;
+            }
+            if (fl) atomicOr(q.sub_flags + sslot, fl);
+            __syncthreads();   // wave_push and block_base are rewritten next step
+        }
+        return;
+    }
     for (uint64_t b0 = (uint64_t)blockIdx.x * span; b0 < r.count; b0 += (uint64_t)gridDim.x * span) {
         // decide every child of the G groups
         uint32_t pushed = 0;   // bit g: this lane's child of group g is appended
@@ -782,7 +863,7 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a)
             const bool act = i < r.count;
             if (act) level_stage_node(nodes, r.base + i, child, stage[grp]);
             lds_order();
-            bool push = false, invalid = false, undecided = false, inexact = false;
+            int d = kChildDone;
             int64_t sslot = 0;
             if (act) {
                 double t[27];
@@ -790,24 +871,10 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a)
                 level_child(stage[grp], child, t, scale, sslot);
                 const bool dead = (__hip_atomic_load(q.sub_flags + sslot, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT) & kFlagInvalid) != 0u;
-                if (!dead) {
-                    const double tau = level_threshold(scale, level);
-                    const double m8 = fmin(fmin(fmin(t[0], t[2]), fmin(t[6], t[8])),
-                                           fmin(fmin(t[18], t[20]), fmin(t[24], t[26])));
-                    double m19 = t[1];
-#pragma unroll
-                    for (int k = 3; k < 26; ++k)
-                        if (k != 6 && k != 8 && k != 18 && k != 20 && k != 24) m19 = fmin(m19, t[k]);
-                    if (m8 <= -tau) invalid = true;
-                    else if (!(m8 > tau)) inexact = true;
-                    else if (m19 > tau) { /* positive on this sub-box */ }
-                    else if (level < a.max_depth) push = true;
-                    else if (m19 <= -tau) undecided = true;
-                    else inexact = true;
-                }
+                if (!dead) d = level_decide(t, scale, level, a.max_depth);
             }
-            const uint32_t fl = (invalid ? kFlagInvalid : 0u) | (undecided ? kFlagUndecided : 0u) |
-                                (inexact ? kFlagExact : 0u);
+            const bool push = d == kChildPush;
+            const uint32_t fl = level_flags(d);
             if (fl) atomicOr(q.sub_flags + sslot, fl);
             const uint64_t pmask = ballot(push);
             if (lane == 0) wave_push[g][wid] = (unsigned int)__popcll(pmask);
@@ -839,18 +906,8 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a)
                     level_child(stage[grp], child, t, scale, sslot);
                     unsigned long long o = off + (unsigned long long)lane_rank(pmask);
                     for (int w = 0; w < wid; ++w) o += wave_push[g][w];
-                    const uint64_t ns = r.next_base + o;
-                    if (ns < cap) {
-                        double* out = reinterpret_cast<double*>(q.nodes + ns);
-#pragma unroll
-                        for (int k = 0; k < 27; ++k) out[k] = t[k];
-                        out[27] = scale;
-                        out[28] = __longlong_as_double(sslot);
-                        out[29] = __longlong_as_double((long long)((uint64_t)(uint32_t)level |
-                                                                   ((uint64_t)(uint32_t)child << 32)));
-                    } else {
+                    if (!level_write(q, r.next_base + o, t, scale, sslot, level, child))
                         atomicOr(q.sub_flags + sslot, kFlagOverflow);
-                    }
                 }
                 lds_order();
             }
