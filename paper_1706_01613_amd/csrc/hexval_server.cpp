@@ -145,7 +145,8 @@ static int run_batch(hexval_server* sv, Slot& sl, const std::vector<ServerReques
 
 static void worker_loop(hexval_server* sv, Slot* sl)
 {
-    hipSetDevice(sv->device);
+    // a worker that cannot select the server's device fails what it takes
+    const bool device_ok = hipSetDevice(sv->device) == hipSuccess;
     for (;;) {
         std::vector<ServerRequest*> batch;
         {
@@ -177,8 +178,15 @@ static void worker_loop(hexval_server* sv, Slot* sl)
         std::vector<int> status(batch.size(), HEXVAL_OK);
         std::vector<std::string> error(batch.size());
         bool alone = batch.size() == 1;
-        if (!alone && run_batch(sv, *sl, batch) != HEXVAL_OK)
+        if (!device_ok) {
+            for (size_t k = 0; k < batch.size(); ++k) {
+                status[k] = fail(HEXVAL_E_HIP, "server worker could not select device %d", sv->device);
+                error[k] = last_error();
+            }
+            alone = false;
+        } else if (!alone && run_batch(sv, *sl, batch) != HEXVAL_OK) {
             alone = true;   // one bad request must not fail the others: run each by itself
+        }
         if (alone) {
             for (size_t k = 0; k < batch.size(); ++k) {
                 status[k] = run_one(sv, *sl, *batch[k]);
