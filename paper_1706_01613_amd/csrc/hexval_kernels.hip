@@ -124,12 +124,16 @@ __device__ __forceinline__ void load_points(const MeshDev& m, int64_t e, V3 p[8]
 // Writes a top-level node for a subdivided element.
 __device__ void write_root(Node* nd, const ElementValues& r, int64_t slot)
 {
+    // the node's first 240 bytes as 15 aligned 16-byte stores
+    double w[30];
 #pragma unroll
-    for (int a = 0; a < 27; ++a) nd->b[fig3_to_tensor(a)] = coefficient(r, a);
-    nd->scale = r.scale;
-    nd->slot = slot;
-    nd->level = 0;
-    nd->orient = 0;
+    for (int a = 0; a < 27; ++a) w[fig3_to_tensor(a)] = coefficient(r, a);
+    w[27] = r.scale;
+    w[28] = __longlong_as_double(slot);
+    w[29] = __longlong_as_double(0);   // level 0, orientation 0
+    double2* out = reinterpret_cast<double2*>(nd);
+#pragma unroll
+    for (int k = 0; k < 15; ++k) out[k] = make_double2(w[2 * k], w[2 * k + 1]);
 }
 
 // Orders this wave's LDS writes before its later LDS reads by other lanes
