@@ -36,6 +36,29 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* global(T* p)
     return (__attribute__((address_space(1))) T*)p;
 }
 
+// A 64-bit value that every lane of the wave holds, as a scalar.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Mesh record mi of a batch table (written before the launch, read only),
+// with scalar loads: mi is the same in every lane of the wave.
+__device__ __forceinline__ MeshDev uniform_mesh_record(const MeshDev* meshes, int mi)
+{
+    typedef __attribute__((address_space(4))) const uint64_t* const_u64;
+    static_assert(sizeof(MeshDev) == 64, "mesh record of 8 words");
+    const const_u64 w = (const_u64)(meshes + mi);
+    uint64_t words[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) words[i] = w[i];
+    MeshDev r;
+    __builtin_memcpy(&r, words, sizeof r);
+    return r;
+}
+
 __device__ __forceinline__ int lane_rank(uint64_t mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -450,13 +473,6 @@ __device__ __forceinline__ void conn_prefetch_loop(const int32_t* conn, int64_t 
     }
 }
 
-// A 64-bit value that every lane of the wave holds, as a scalar.
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
-{
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
 
 __device__ __forceinline__ void gather8(const double* points, const int idx[8], V3 p[8])
 {
@@ -480,17 +496,9 @@ __device__ __forceinline__ void batch_prefetch_loop(const MeshDev* meshes, const
     const int wave_base = threadIdx.x & ~63;
     // scalar loads: both tables are written before the launch and only read here
     typedef __attribute__((address_space(4))) const int32_t* const_i32;
-    typedef __attribute__((address_space(4))) const uint64_t* const_u64;
-    static_assert(sizeof(MeshDev) == 64, "mesh record of 8 words");
     auto mesh_of = [&](int64_t t, int& mi) {
         mi = ((const_i32)tile_mesh)[(int64_t)uniform_u64((uint64_t)t)];
-        const const_u64 w = (const_u64)(meshes + mi);
-        uint64_t words[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) words[i] = w[i];
-        MeshDev r;
-        __builtin_memcpy(&r, words, sizeof r);
-        return r;
+        return uniform_mesh_record(meshes, mi);
     };
     auto prefetch = [&](int64_t t, const MeshDev& m) {
         int64_t e = (t - m.tile_begin) * (int64_t)blockDim.x + threadIdx.x;
