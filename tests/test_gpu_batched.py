@@ -140,3 +140,19 @@ def test_batched_tiny_queue_rounds_equal_alone(precision):
     for k, ((V, C), v) in enumerate(zip(meshes, vs)):
         va, _ = _alone(torch, V, C, precision=precision)
         assert torch.equal(v, va), k
+
+
+def test_batched_without_min_outputs_and_prepared_args():
+    # min_coeffs may be omitted; prepared C arrays give the same results on
+    # repeated calls
+    torch = torch_cuda()
+    meshes = list(synth.batched_meshes_torch(25, lo=1.0, hi=4.0, seed=41))
+    vs = [torch.empty(C.shape[0], dtype=torch.uint8, device="cuda") for _, C in meshes]
+    args = hx.BatchArgs([hx.make_mesh(V, C) for V, C in meshes], vs)
+    opts = hx.make_opts(stream=torch.cuda.current_stream())
+    for rep in range(2):
+        hx.hexval_check_batched(args, opts)
+        torch.cuda.synchronize()
+        for k, ((V, C), v) in enumerate(zip(meshes, vs)):
+            va, _ = _alone(torch, V, C)
+            assert torch.equal(v, va), (rep, k)
