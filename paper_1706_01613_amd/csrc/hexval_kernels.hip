@@ -163,13 +163,13 @@ __device__ void write_root(Node* nd, const ElementValues& r, int64_t slot)
 // (a compiler barrier: one wave's LDS accesses complete in issue order).
 __device__ __forceinline__ void lds_order() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
 
-// Elements the first pass sends to subdivision are held per wave in LDS and
-// appended to the subdivision list up to kPushBuf at a time, with one atomic:
-// on invalid-heavy meshes most waves send some element, and one atomic per
-// wave and tile on the single list counter serialises the pass.  Their
-// verdict (pending, or deferred when the list is full) is written when they
-// are appended.  Every lane of the wave calls push_flush; each kernel that
-// fills a buffer flushes it after its last tile.
+// Elements a first pass sends on (to subdivision, or from the FP32 filter to
+// the FP64 recheck) are held per wave in LDS and appended to their list up to
+// kPushBuf at a time, with one atomic: on invalid-heavy meshes most waves send
+// some element, and one atomic per wave and tile on the single list counter
+// serialises the pass.  Their verdict (pending, or deferred when the list is
+// full) is written when they are appended.  Every lane of the wave calls
+// push_flush; each kernel that fills a buffer flushes it after its last tile.
 constexpr int kPushBuf = 256;
 
 struct PushBuf {
@@ -178,6 +178,7 @@ struct PushBuf {
     int n;                                              // entries held (wave-uniform)
 };
 
+// The buffers of the (at most 4) waves of a block, and this wave's.
 #define HX_PUSH_STORAGE                                              \
     __shared__ int64_t push_elem_[4 * kPushBuf];                     \
     __shared__ int32_t push_mesh_[4 * kPushBuf];                     \
@@ -193,7 +194,10 @@ struct ListRef {
     uint64_t cap;
 };
 
-__device__ __forceinline__ ListRef sub_list(const QueueDev& q) { return {&q.cnt->n_sub, q.sub_elem, q.sub_mesh, q.root_cap}; }
+__device__ __forceinline__ ListRef sub_list(const QueueDev& q)
+{
+    return {&q.cnt->n_sub, q.sub_elem, q.sub_mesh, q.root_cap};
+}
 __device__ __forceinline__ ListRef recheck_list(const QueueDev& q)
 {
     return {&q.cnt->n_list, q.list_elem, q.list_mesh, q.list_cap};
