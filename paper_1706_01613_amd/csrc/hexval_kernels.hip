@@ -3,8 +3,14 @@
 //   k_top_f64      first pass, one element per lane: gather the 8 corners,
 //                  20 triple products (Section 5), Table 3, certified
 //                  decisions of Section 6 steps 2 and 4; ambiguous elements
-//                  are compacted (ballot + one atomic per wave) into the
-//                  subdivision queue, uncertain ones into the exact list.
+//                  go to the subdivision list through a per-wave LDS buffer,
+//                  uncertain ones to the exact list (ballot + one atomic per
+//                  wave).  k_filter_f32: the same in FP32 with a forward
+//                  bound, the rest to the FP64 recheck list.
+//   k_minj_*       certified bounds of min J: first pass, levels, fold.
+//   k_corner_*     Test 1 (corner values only) and corner quality.
+//   k_quad_*       linear quadrangles (Section 2.1).
+//   k_exact_device the exact tier in 256-bit integers.
 //   k_roots        root sub-boxes (level 0) of the subdivided elements.
 //   k_level        one level of the subdivision: eight lanes per stored
 //                  sub-box, one lane per child (de Casteljau at 1/2);
