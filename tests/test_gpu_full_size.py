@@ -91,3 +91,30 @@ def test_quad_lattice_8000_squared_every_element():
     assert np.array_equal(v, ref["verdict"])
     assert np.abs(m - ref["min_j"]).max() <= 1e-13
     assert 0 < np.count_nonzero(v == hx.INVALID) < v.size
+
+
+def test_more_elements_than_int32_can_index():
+    """2^31 + 257 hexes (the connectivity of a 20^3 lattice with 5% of its
+    vertices jittered, repeated; 69 GB of connectivity): every element index
+    past 2^31 - 1 is addressed in 64-bit arithmetic, and every copy of the
+    small mesh gets the verdicts of the small mesh alone."""
+    torch = torch_cuda()
+    V, C = synth.warped_lattice(20, 20, 20, seed=7, jitter_fraction=0.05)
+    m = C.shape[0]
+    n = (1 << 31) + 257
+    Vd, Cs = to_dev(torch, V), to_dev(torch, C)
+    v_small, _, _ = hx.check(Vd, Cs)
+    torch.cuda.synchronize()
+    assert_parity(v_small.cpu().numpy(), None, V, C, label="20^3 lattice")
+    reps = (n + m - 1) // m
+    _say(f"repeating {m} hexes {reps} times: {n} elements")
+    Cd = Cs.repeat(reps, 1)[:n]
+    v, _, st = hx.check(Vd, Cd, want_min=False, stats=True, block_threads=256, grid_blocks=1024)
+    torch.cuda.synchronize()
+    _say(f"stats {st}")
+    assert st["n_elements"] == n
+    full = n // m
+    assert torch.equal(v[:full * m].view(full, m), v_small.expand(full, m))
+    assert torch.equal(v[full * m:], v_small[:n - full * m])
+    del Cd, v
+    torch.cuda.empty_cache()
