@@ -114,6 +114,18 @@ def test_closed_form_families(max_depth):
     assert_parity(v, m, P, max_depth=max_depth, label=f"families d={max_depth}")
 
 
+def test_deepest_depth_cap():
+    # the largest cap (20): families that end by level 11 (the flat prism,
+    # whose live boxes grow as 4^L, is left out)
+    torch = torch_cuda()
+    fam = [_twisted(t) for t in (30, 120, 180)]
+    fam += [_prism(e) for e in (0.25, 2.0 ** -10, 2.0 ** -20, -(2.0 ** -10), -(2.0 ** -20))]
+    P = np.stack(fam)
+    v, m, st = _run(torch, P, max_depth=20)
+    assert st["max_level"] == 11
+    assert_parity(v, m, P, max_depth=20, label="families d=20")
+
+
 def test_exact_tier_integer_lattice():
     # small-integer hexes: many values exactly 0 -> exact tier on both sides
     torch = torch_cuda()
