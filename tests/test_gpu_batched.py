@@ -156,3 +156,23 @@ def test_batched_without_min_outputs_and_prepared_args():
         for k, ((V, C), v) in enumerate(zip(meshes, vs)):
             va, _ = _alone(torch, V, C)
             assert torch.equal(v, va), (rep, k)
+
+
+def test_batched_index_validation():
+    # index validation on: a batch whose meshes have an out-of-range index
+    # here and there gets BAD_INPUT exactly there, and otherwise the
+    # verdicts of each mesh checked alone
+    torch = torch_cuda()
+    meshes = list(synth.batched_meshes_torch(12, lo=2.0, hi=4.0, seed=51))
+    bad = {}
+    for k in (2, 7, 11):
+        V, C = meshes[k]
+        e = C.shape[0] // 2
+        C[e, 5] = V.shape[0] + 3
+        bad[k] = e
+    vs, _ = _batched(torch, meshes, hx.FP64, validate_indices=True)
+    for k, ((V, C), v) in enumerate(zip(meshes, vs)):
+        va, _ = _alone(torch, V, C, validate_indices=True)
+        assert torch.equal(v, va), k
+        if k in bad:
+            assert int(v[bad[k]]) == hx.BAD_INPUT, k
