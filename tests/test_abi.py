@@ -119,3 +119,25 @@ def test_batch_args_marshal_once():
     assert [a.verdicts[i] for i in range(7)] == [3000 + i for i in range(7)]
     assert [a.min_coeffs[i] or 0 for i in range(7)] == [4000 + i if i % 2 else 0 for i in range(7)]
     assert hx.BatchArgs(meshes, [1] * 7).min_coeffs is None
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    # without the built library the binding raises; it never falls back to
+    # anything else (checked in a fresh interpreter, so that the library this
+    # process already loaded does not interfere)
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_1706_01613_amd import hexval as hx\n"
+        "hx.LIB_PATH = %r\n"
+        "try:\n"
+        "    hx.lib()\n"
+        "except hx.HexvalError as e:\n"
+        "    print('raised', e)\n"
+        "    sys.exit(0)\n"
+        "sys.exit(1)\n"
+    ) % (str(ROOT), str(tmp_path / "libhexval.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "raised" in r.stdout
