@@ -63,7 +63,7 @@ enum {
     HEXVAL_E_HIP = 2,   /* HIP runtime error, no usable gfx950 device, or kernel failure */
     HEXVAL_E_NOMEM = 3, /* device or host allocation failed */
     HEXVAL_E_QUEUE = 4, /* the subdivision queue cannot hold one element's tree */
-    HEXVAL_E_BUSY = 5   /* server: no capacity for this request (never returned by submit) */
+    HEXVAL_E_BUSY = 5   /* server: one request's uploads alone exceed what the budget leaves */
 };
 
 /* Precision of the first pass. */
@@ -251,9 +251,11 @@ int hexval_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts, do
  * concurrently on the workers' streams.  Outputs never depend on how
  * requests were grouped.  A request whose mesh pointers are device pointers
  * references that memory (the caller keeps it alive until the request is
- * done); with host_points/host_conn set the server copies the mesh to the
- * device itself (pinned staging, copy stream) and counts that copy in the
- * footprint. */
+ * done); with host_points/host_conn set the worker copies the mesh to the
+ * device itself, on its stream, into an upload buffer that it keeps between
+ * requests.  That buffer counts against the budget while the worker holds
+ * it; a free worker gives its buffer back when the oldest waiting request
+ * does not fit. */
 typedef struct hexval_server hexval_server_t;
 
 typedef struct {
@@ -265,8 +267,10 @@ typedef struct {
 } hexval_request_t;
 
 /* opts: precision, max_depth, validate_indices apply to every request (stream and
- * stats are ignored).  hbm_budget_bytes: device memory the server may hold for
- * requests in flight (queues + uploaded meshes), > 0.  max_slots: 1..64. */
+ * stats are ignored).  hbm_budget_bytes: device memory the server may hold
+ * (the workers' workspaces, allocated at creation, plus their upload
+ * buffers), > 0; HEXVAL_E_ARG when the workspaces alone exceed it.
+ * max_slots: 1..64. */
 int hexval_server_create(const hexval_opts_t* opts, int64_t hbm_budget_bytes, int32_t max_slots,
                          hexval_server_t** server);
 /* Never blocks on the GPU.  *ticket identifies the request.  Returns
@@ -275,7 +279,9 @@ int hexval_server_submit(hexval_server_t* server, const hexval_request_t* reques
                          uint64_t* ticket);
 /* *done = 1 once the outputs of ticket are final; latency_ms (optional) =
  * submit-to-completion wall time.  The status of the finished request is the
- * return value once done. */
+ * return value once done.  A ticket is forgotten once poll has reported it
+ * done or wait has returned it (and no other thread still waits on it):
+ * later calls with it return HEXVAL_E_ARG. */
 int hexval_server_poll(hexval_server_t* server, uint64_t ticket, int* done, double* latency_ms);
 /* Blocks until ticket is done; returns its status. */
 int hexval_server_wait(hexval_server_t* server, uint64_t ticket, double* latency_ms);

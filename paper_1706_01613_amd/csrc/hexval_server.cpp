@@ -13,6 +13,12 @@
 // the slots' streams, so requests arriving while others are on the GPU join
 // as soon as a slot and memory are free.  The arithmetic of an element never
 // depends on the batch it runs in.
+//
+// Uploads go to one buffer per slot that is kept between requests.  The
+// bytes a slot has reserved for it count against the budget for as long as
+// the slot holds them; a free slot that holds some gives them back when the
+// oldest request does not fit, so the budget bounds what the server holds,
+// not only what is in flight.
 #include <hip/hip_runtime.h>
 
 #include <string.h>
@@ -45,6 +51,7 @@ struct ServerRequest {
     uint64_t upload_bytes = 0;
     Clock::time_point t_submit, t_done;
     bool done = false;
+    int waiters = 0;   // threads in hexval_server_wait on this ticket
     int status = HEXVAL_OK;
     std::string error;
 };
@@ -52,10 +59,16 @@ struct ServerRequest {
 struct Slot {
     hipStream_t stream = nullptr;
     Workspace* ws = nullptr;
-    double* up_points = nullptr;
-    int32_t* up_conn = nullptr;
-    uint64_t up_points_cap = 0, up_conn_cap = 0;
+    uint8_t* up = nullptr;      // upload buffer: points, then connectivity
+    uint64_t up_cap = 0;        // bytes allocated in up (<= up_reserved)
+    uint64_t up_reserved = 0;   // bytes of the budget this slot holds for up (under the lock)
     std::thread worker;
+    ~Slot()
+    {
+        delete ws;
+        if (up) hipFree(up);
+        if (stream) hipStreamDestroy(stream);
+    }
 };
 
 }  // namespace hexval
@@ -65,7 +78,7 @@ struct hexval_server {
     int device = 0;
     int64_t budget = 0;
     int64_t reserved = 0;      // workspaces
-    int64_t in_use = 0;        // uploads of admitted requests
+    int64_t in_use = 0;        // upload bytes reserved by the slots
     uint64_t next_ticket = 1;
     bool stop = false;
     std::mutex mu;
@@ -77,47 +90,55 @@ struct hexval_server {
 
 namespace hexval {
 
+// Byte offset of the connectivity in a slot's upload buffer.
+static uint64_t points_bytes(const hexval_request_t& r)
+{
+    const hexval_mesh_t& m = r.mesh;
+    if (!r.host_points) return 0;
+    const uint64_t np = m.connectivity || r.host_conn ? (uint64_t)m.n_points * 3 : (uint64_t)m.n * 24;
+    return (np * 8 + 255) & ~255ull;
+}
+
 static uint64_t upload_bytes(const hexval_request_t& r)
 {
-    uint64_t b = 0;
-    const hexval_mesh_t& m = r.mesh;
-    if (r.host_points) b += (m.connectivity || r.host_conn ? (uint64_t)m.n_points * 3 : (uint64_t)m.n * 24) * 8;
-    if (r.host_conn) b += (uint64_t)m.n * 8 * 4;
+    uint64_t b = points_bytes(r);
+    if (r.host_conn) b += (uint64_t)r.mesh.n * 8 * 4;
     return (b + 255) & ~255ull;
+}
+
+// Upload bytes the slot would add to the server's total by taking rq.
+static int64_t growth(const Slot& sl, const ServerRequest& rq)
+{
+    return rq.upload_bytes > sl.up_reserved ? (int64_t)(rq.upload_bytes - sl.up_reserved) : 0;
 }
 
 static int run_one(hexval_server* sv, Slot& sl, ServerRequest& rq)
 {
     hexval_request_t r = rq.req;
     hexval_mesh_t m = r.mesh;
+    if (rq.upload_bytes > sl.up_cap) {
+        // the bytes are reserved already (admission); the slot's stream is idle
+        if (sl.up) hipFree(sl.up);
+        sl.up = nullptr;
+        sl.up_cap = 0;
+        if (hipMalloc(&sl.up, rq.upload_bytes) != hipSuccess) {
+            sl.up = nullptr;
+            return fail(HEXVAL_E_NOMEM, "server upload buffer of %llu bytes", (unsigned long long)rq.upload_bytes);
+        }
+        sl.up_cap = rq.upload_bytes;
+    }
     if (r.host_points) {
         const bool shared = m.connectivity || r.host_conn;
         const uint64_t np = shared ? (uint64_t)m.n_points * 3 : (uint64_t)m.n * 24;
-        if (np > sl.up_points_cap) {
-            if (sl.up_points) hipFree(sl.up_points);
-            sl.up_points = nullptr;
-            sl.up_points_cap = 0;
-            if (hipMalloc(&sl.up_points, np * 8) != hipSuccess)
-                return fail(HEXVAL_E_NOMEM, "server upload buffer of %llu bytes", (unsigned long long)(np * 8));
-            sl.up_points_cap = np;
-        }
-        if (hipMemcpyAsync(sl.up_points, r.host_points, np * 8, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
+        if (hipMemcpyAsync(sl.up, r.host_points, np * 8, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
             return fail(HEXVAL_E_HIP, "server upload of points failed");
-        m.points = sl.up_points;
+        m.points = reinterpret_cast<const double*>(sl.up);
     }
     if (r.host_conn) {
-        const uint64_t nc = (uint64_t)m.n * 8;
-        if (nc > sl.up_conn_cap) {
-            if (sl.up_conn) hipFree(sl.up_conn);
-            sl.up_conn = nullptr;
-            sl.up_conn_cap = 0;
-            if (hipMalloc(&sl.up_conn, nc * 4) != hipSuccess)
-                return fail(HEXVAL_E_NOMEM, "server upload buffer of %llu bytes", (unsigned long long)(nc * 4));
-            sl.up_conn_cap = nc;
-        }
-        if (hipMemcpyAsync(sl.up_conn, r.host_conn, nc * 4, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
+        int32_t* conn = reinterpret_cast<int32_t*>(sl.up + points_bytes(r));
+        if (hipMemcpyAsync(conn, r.host_conn, (uint64_t)m.n * 32, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
             return fail(HEXVAL_E_HIP, "server upload of connectivity failed");
-        m.connectivity = sl.up_conn;
+        m.connectivity = conn;
     }
     hexval_opts_t o = sv->opts;
     o.stream = sl.stream;
@@ -149,23 +170,32 @@ static void worker_loop(hexval_server* sv, Slot* sl)
     const bool device_ok = hipSetDevice(sv->device) == hipSuccess;
     for (;;) {
         std::vector<ServerRequest*> batch;
+        bool give_back = false;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
+            const int64_t room = sv->budget - sv->reserved;
             sv->cv_work.wait(lk, [&] {
-                if (sv->stop && sv->pending.empty()) return true;
-                if (sv->pending.empty()) return false;
-                return sv->in_use + (int64_t)sv->pending.front()->upload_bytes <= sv->budget - sv->reserved;
+                if (sv->pending.empty()) return sv->stop;
+                // a slot that holds upload bytes the oldest request needs elsewhere gives them back
+                return sv->in_use + growth(*sl, *sv->pending.front()) <= room || sl->up_reserved > 0;
             });
             if (sv->pending.empty()) return;
             ServerRequest* rq = sv->pending.front();
-            sv->pending.pop_front();
-            sv->in_use += (int64_t)rq->upload_bytes;
-            batch.push_back(rq);
+            if (sv->in_use + growth(*sl, *rq) > room) {
+                sv->in_use -= (int64_t)sl->up_reserved;
+                sl->up_reserved = 0;
+                give_back = true;
+            } else {
+                sv->pending.pop_front();
+                sv->in_use += growth(*sl, *rq);
+                sl->up_reserved = std::max(sl->up_reserved, rq->upload_bytes);
+                batch.push_back(rq);
+            }
             // device-resident requests queued behind it join its call (in
             // order: the first one that needs an upload, or would overflow
             // the batch, stops the batch)
             int64_t hexes = rq->req.mesh.n;
-            if (rq->upload_bytes == 0 && hexes <= kBatchHexes) {
+            if (!give_back && rq->upload_bytes == 0 && hexes <= kBatchHexes) {
                 while (!sv->pending.empty() && (int)batch.size() < kMaxBatch) {
                     ServerRequest* nx = sv->pending.front();
                     if (nx->upload_bytes != 0 || hexes + nx->req.mesh.n > kBatchHexes) break;
@@ -174,6 +204,14 @@ static void worker_loop(hexval_server* sv, Slot* sl)
                     hexes += nx->req.mesh.n;
                 }
             }
+        }
+        if (give_back) {
+            // nothing of this slot is on its stream: the last request it ran has completed
+            if (sl->up) hipFree(sl->up);
+            sl->up = nullptr;
+            sl->up_cap = 0;
+            sv->cv_work.notify_all();
+            continue;
         }
         std::vector<int> status(batch.size(), HEXVAL_OK);
         std::vector<std::string> error(batch.size());
@@ -193,12 +231,14 @@ static void worker_loop(hexval_server* sv, Slot* sl)
                 if (status[k]) error[k] = last_error();
             }
         }
+        // a call that failed part-way may have left copies or kernels on the
+        // stream: none may touch the caller's buffers once a request is done
+        if (device_ok) hipStreamSynchronize(sl->stream);
         {
             std::lock_guard<std::mutex> lk(sv->mu);
             const auto now = Clock::now();
             for (size_t k = 0; k < batch.size(); ++k) {
                 ServerRequest* rq = batch[k];
-                sv->in_use -= (int64_t)rq->upload_bytes;
                 rq->status = status[k];
                 rq->error = error[k];
                 rq->t_done = now;
@@ -244,16 +284,16 @@ int hexval_server_create(const hexval_opts_t* opts, int64_t hbm_budget_bytes, in
     sv->budget = hbm_budget_bytes;
     sv->reserved = per_slot * max_slots;
     for (int i = 0; i < max_slots; ++i) {
+        // on failure the slots made so far are freed with sv (no worker runs yet)
         std::unique_ptr<Slot> sl(new Slot());
-        if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess)
+        if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) {
+            sl->stream = nullptr;
             return fail(HEXVAL_E_HIP, "hipStreamCreate failed");
+        }
         sl->ws = new Workspace();
         sl->ws->device = dev;
-        if ((rc = sl->ws->init()) || (rc = sl->ws->ensure(node_cap, list_cap, kMaxBatch, batch_tiles))) {
-            delete sl->ws;
-            hipStreamDestroy(sl->stream);
+        if ((rc = sl->ws->init()) || (rc = sl->ws->ensure(node_cap, list_cap, kMaxBatch, batch_tiles)))
             return rc;
-        }
         sv->slots.push_back(std::move(sl));
     }
     for (auto& sl : sv->slots) sl->worker = std::thread(worker_loop, sv.get(), sl.get());
@@ -289,11 +329,15 @@ int hexval_server_submit(hexval_server_t* sv, const hexval_request_t* request, u
     return HEXVAL_OK;
 }
 
+// Reports a finished request (under the lock) and forgets its ticket once no
+// other thread waits on it.
 static int finish(hexval_server_t* sv, ServerRequest* rq, double* latency_ms)
 {
     if (latency_ms) latency_ms[0] = std::chrono::duration<double, std::milli>(rq->t_done - rq->t_submit).count();
-    if (rq->status) fail(rq->status, "%s", rq->error.c_str());
-    return rq->status;
+    const int status = rq->status;
+    if (status) fail(status, "%s", rq->error.c_str());
+    if (rq->waiters == 0) sv->all.erase(rq->ticket);
+    return status;
 }
 
 int hexval_server_poll(hexval_server_t* sv, uint64_t ticket, int* done, double* latency_ms)
@@ -314,7 +358,9 @@ int hexval_server_wait(hexval_server_t* sv, uint64_t ticket, double* latency_ms)
     auto it = sv->all.find(ticket);
     if (it == sv->all.end()) return fail(HEXVAL_E_ARG, "unknown ticket %llu", (unsigned long long)ticket);
     ServerRequest* rq = it->second.get();
+    ++rq->waiters;
     sv->cv_done.wait(lk, [&] { return rq->done; });
+    --rq->waiters;
     return finish(sv, rq, latency_ms);
 }
 
@@ -328,14 +374,11 @@ int hexval_server_destroy(hexval_server_t* sv)
     sv->cv_work.notify_all();
     for (auto& sl : sv->slots)
         if (sl->worker.joinable()) sl->worker.join();
-    for (auto& sl : sv->slots) {
-        hipSetDevice(sv->device);
-        delete sl->ws;
-        if (sl->up_points) hipFree(sl->up_points);
-        if (sl->up_conn) hipFree(sl->up_conn);
-        hipStreamDestroy(sl->stream);
-    }
-    delete sv;
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    hipSetDevice(sv->device);
+    delete sv;   // the slots free their workspaces, upload buffers and streams
+    if (prev >= 0) hipSetDevice(prev);
     return HEXVAL_OK;
 }
 

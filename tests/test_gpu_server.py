@@ -141,3 +141,73 @@ def test_server_bad_request_does_not_fail_its_batch():
                 assert torch.equal(v, alone[i]), k
     finally:
         hx.hexval_server_destroy(sv)
+
+
+def _slot_bytes(opts):
+    # the per-slot workspace size, as create reports it when the budget is too small
+    with pytest.raises(hx.HexvalError) as e:
+        hx.hexval_server_create(opts, 1, 1)
+    msg = str(e.value)
+    return int(msg[msg.rindex("(") + 1:].split()[0])
+
+
+def test_server_upload_buffers_fit_the_budget():
+    # room for the slot workspaces plus a little over two of the smaller
+    # uploads: slots holding upload buffers from earlier requests must give
+    # them back for a larger one to run, and every request still completes
+    torch = torch_cuda()
+    meshes = [synth.near_degenerate_mesh_torch(s, seed=40 + k) for k, s in enumerate((20000, 22000, 36000))]
+    host = [(V.cpu().pin_memory(), C.cpu().pin_memory()) for V, C in meshes]
+    alone = [_alone(torch, V, C, hx.FP64) for V, C in meshes]
+    up = [(V.numel() * 8 + 255) // 256 * 256 + C.numel() * 4 for V, C in meshes]
+    opts = hx.make_opts()
+    slots = 3
+    room = max(up[0] + up[1], up[2]) + 4096
+    # buffers for the second and the third request cannot be held together
+    assert up[1] + up[2] > room
+    sv = hx.hexval_server_create(opts, slots * _slot_bytes(opts) + room, slots)
+    try:
+        idx = np.array([0, 1, 2, 0, 1, 2, 1, 0, 2, 2, 0, 1])
+        sizes = [meshes[i][1].shape[0] for i in idx]
+        arena = torch.empty(loadgen.arena_bytes(sizes), dtype=torch.uint8, device="cuda")
+        tmpl = _templates(host, host=True)
+        for t, (V, C) in zip(tmpl, host):
+            t.mesh.n_points = V.shape[0]
+        _say("upload buffers: 12 requests, 3 slots")
+        _, st, off, _ = loadgen.run(sv, np.zeros(12), idx, tmpl, arena)
+        torch.cuda.synchronize()
+        assert (st == hx.OK).all()
+        for k, i in enumerate(idx):
+            v, m = _outputs(torch, arena, int(off[k]), sizes[k])
+            assert torch.equal(v, alone[i][0]), k
+            assert torch.equal(torch.nan_to_num(m, 7.0), torch.nan_to_num(alone[i][1], 7.0)), k
+    finally:
+        hx.hexval_server_destroy(sv)
+
+
+def test_server_ticket_is_forgotten_once_reported():
+    torch = torch_cuda()
+    V, C = synth.near_degenerate_mesh_torch(3000, seed=77)
+    v = torch.empty(C.shape[0], dtype=torch.uint8, device="cuda")
+    sv = hx.hexval_server_create(hx.make_opts(), 8 << 30, 2)
+    try:
+        r = hx.hexval_request_t()
+        r.mesh = hx.make_mesh(V, C)
+        r.verdicts = v.data_ptr()
+        t1 = hx.hexval_server_submit(sv, r)
+        assert hx.hexval_server_wait(sv, t1) >= 0.0
+        with pytest.raises(hx.HexvalError) as e:
+            hx.hexval_server_poll(sv, t1)
+        assert e.value.status == hx.E_ARG
+        t2 = hx.hexval_server_submit(sv, r)
+        assert t2 != t1
+        done = False
+        while not done:
+            done, lat = hx.hexval_server_poll(sv, t2)
+        assert lat >= 0.0
+        with pytest.raises(hx.HexvalError):
+            hx.hexval_server_wait(sv, t2)
+        torch.cuda.synchronize()
+        assert torch.equal(v, _alone(torch, V, C, hx.FP64)[0])
+    finally:
+        hx.hexval_server_destroy(sv)
