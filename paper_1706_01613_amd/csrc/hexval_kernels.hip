@@ -1042,8 +1042,8 @@ __device__ __forceinline__ void minj_write(const MinjArgs& a, int64_t e, double 
 {
     if (st <= 2) {
         const double mg = minj_margin(scale, a.max_depth);
-        lo = nextafter(lo - mg, -HUGE_VAL);
-        hi = nextafter(hi + mg, HUGE_VAL);
+        lo = next_down(lo - mg);
+        hi = next_up(hi + mg);
     } else {
         lo = hi = __builtin_nan("");
     }
@@ -1081,7 +1081,7 @@ __device__ void minj_element(const MinjArgs& a, int64_t e, bool active, const V3
                 lo = r.min27;
                 hi = r.m20;
                 scale = r.scale;
-                const double tol = a.mj.rtol * scale / 6.0;
+                const double tol = a.mj.rtol * (1.0 / 6.0) * scale;
                 if (lo >= hi - tol) st = kMjConverged;
                 else if (a.max_depth == 0) st = kMjCapped;
             }
@@ -1239,7 +1239,7 @@ __global__ __launch_bounds__(256) void k_minj_level(MinjArgs a)
         x.sslot = (int64_t)__double_as_longlong(nd[28]);
         x.orient = (int)((uint64_t)__double_as_longlong(nd[29]) >> 32);
         x.U = of_ord(R[x.sslot]);
-        const bool close = x.lo >= x.U - a.mj.rtol * x.scale / 6.0;
+        const bool close = x.lo >= x.U - a.mj.rtol * (1.0 / 6.0) * x.scale;
         x.split = L == 0 || (!close && L < a.max_depth);
         x.capped = !x.split && !close;
         return x;

@@ -6,6 +6,7 @@
 #pragma once
 
 #include <stdint.h>
+#include <string.h>
 #include <math.h>
 
 #ifndef HEXVAL_HD
@@ -17,6 +18,27 @@
 #endif
 
 namespace hexval {
+
+// nextafter(x, -inf) and nextafter(x, +inf) from the bit pattern (one
+// integer step away from zero or towards it), without the library call's
+// general two-argument handling.
+HEXVAL_HD double next_down(double x)
+{
+    if (x != x || x == -HUGE_VAL) return x;
+    int64_t b;
+    if (x == 0.0) {
+        b = 1;                          // the smallest subnormal, negated below
+        double d;
+        memcpy(&d, &b, 8);
+        return -d;
+    }
+    memcpy(&b, &x, 8);
+    b += x > 0.0 ? -1 : 1;
+    double d;
+    memcpy(&d, &b, 8);
+    return d;
+}
+HEXVAL_HD double next_up(double x) { return -next_down(-x); }
 
 // u = 2^-53 (binary64 unit roundoff).
 constexpr double kU64 = 1.1102230246251565e-16;

@@ -214,6 +214,15 @@ void hexval_emul_lean(const double* pts, const int32_t* conn, int64_t n, int pre
 }
 
 // Bound constants of the kernels: {tau_value, tau_coeff, tau_level, u64, u32}.
+// The kernels' outward rounding of min-J bounds, element-wise.
+void hexval_emul_next(const double* x, int64_t n, double* down, double* up)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        down[i] = next_down(x[i]);
+        up[i] = next_up(x[i]);
+    }
+}
+
 void hexval_emul_constants(double* out)
 {
     out[0] = kTauValue;

@@ -178,3 +178,24 @@ def test_fp32_filter_decisions_agree_with_oracle(emul):
     assert decided.mean() > 0.8
     # the near-degenerate corners are never certified in FP32
     assert not decided[100000:120000].any()
+
+
+def test_outward_rounding_is_nextafter(emul):
+    # the min-J kernels widen their bounds with next_down / next_up, written
+    # from the bit pattern: they must equal nextafter towards -inf / +inf
+    rng = np.random.default_rng(11)
+    special = np.array([0.0, -0.0, 1.0, -1.0, np.inf, -np.inf, np.nan, 5e-324, -5e-324,
+                        2.2250738585072014e-308, -2.2250738585072014e-308, np.finfo(float).max,
+                        -np.finfo(float).max, 1e-300, 3.5])
+    x = np.concatenate([special, rng.integers(0, 2 ** 63, 200000, dtype=np.int64).view(np.float64),
+                        -rng.integers(0, 2 ** 63, 200000, dtype=np.int64).view(np.float64)])
+    down = np.empty_like(x)
+    up = np.empty_like(x)
+    emul.hexval_emul_next.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+    emul.hexval_emul_next(x.ctypes.data, x.size, down.ctypes.data, up.ctypes.data)
+    with np.errstate(over="ignore", invalid="ignore"):
+        want_down = np.nextafter(x, -np.inf)
+        want_up = np.nextafter(x, np.inf)
+    assert np.array_equal(down.view(np.int64)[~np.isnan(x)], want_down.view(np.int64)[~np.isnan(x)])
+    assert np.array_equal(up.view(np.int64)[~np.isnan(x)], want_up.view(np.int64)[~np.isnan(x)])
+    assert np.isnan(down[np.isnan(x)]).all() and np.isnan(up[np.isnan(x)]).all()
