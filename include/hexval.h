@@ -253,7 +253,7 @@ int hexval_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts, do
  * references that memory (the caller keeps it alive until the request is
  * done); with host_points/host_conn set the worker copies the mesh to the
  * device itself, on its stream, into an upload buffer that it keeps between
- * requests.  That buffer counts against the budget while the worker holds
+ * requests (the host copies, too, stay alive until the request is done).  That buffer counts against the budget while the worker holds
  * it; a free worker gives its buffer back when the oldest waiting request
  * does not fit. */
 typedef struct hexval_server hexval_server_t;
