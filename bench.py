@@ -411,8 +411,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only (elements are independent; "
-              "see the sharding notes in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py: measures one GPU only (elements are independent, so several GPUs "
+              "would each check their own share of the elements). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

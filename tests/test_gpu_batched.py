@@ -100,26 +100,26 @@ def test_launch_shape_does_not_change_results():
     assert torch.equal(vs[0], ref[0]) and torch.equal(vs[1], ref[0])
 
 
-def test_config4_full_size_batched():
+def test_batched_10000_lattices_full_size():
     """10,000 meshes, hex counts log-uniform in [1e2, 1e6] (about 1.1e9 hexes),
     every vertex jittered by U(0, 0.6) cell, FP32 filter + FP64, cap 6, one
     persistent launch; a sample of meshes is checked against the oracle."""
     torch = torch_cuda()
-    _say("config 4: generating 10,000 meshes on the device")
+    _say("10,000 jittered lattices: generating the meshes on the device")
     meshes = list(synth.batched_meshes_torch(10000, seed=4))
     total = sum(C.shape[0] for _, C in meshes)
-    _say(f"config 4: {total} hexes")
+    _say(f"10,000 jittered lattices: {total} hexes")
     st = hx.hexval_stats_t()
     st.timing = 1
     vs, ms = _batched(torch, meshes, hx.FP32_FILTER, stats=st)
-    _say(f"config 4 stats: {st.as_dict()}")
+    _say(f"10,000 jittered lattices, stats: {st.as_dict()}")
     assert st.n_elements == total and total > 5e8
     rng = np.random.default_rng(0)
     sizes = np.array([C.shape[0] for _, C in meshes])
     sample = list(rng.choice(len(meshes), 12, replace=False)) + [int(sizes.argmax())]
     for k in sample:
         V, C = meshes[k]
-        _say(f"config 4: oracle on mesh {k} ({C.shape[0]} hexes)")
+        _say(f"10,000 jittered lattices: oracle on mesh {k} ({C.shape[0]} hexes)")
         assert_parity(vs[k].cpu().numpy(), None, V.cpu().numpy(), C.cpu().numpy(), label=f"mesh {k}")
 
 

@@ -44,7 +44,7 @@ def test_corner_independent_hexes_full():
     P = synth.independent_hexes(1000000, seed=0)
     t1, q, st = _gpu(torch, P)
     _say(f"stats {st}")
-    _compare(t1, q, P, label="config 1")
+    _compare(t1, q, P, label="1M independent hexes")
 
 
 def test_corner_lattice_with_index_validation():

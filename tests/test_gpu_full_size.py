@@ -30,24 +30,24 @@ def _check_all(v, m, V, C, label):
         assert_parity(v[lo:hi], None if m is None else m[lo:hi], V, C[lo:hi], label=f"{label}[{lo}:{hi}]")
 
 
-def test_config2_400_cubed_lattice_every_element():
+def test_warped_lattice_400_cubed_every_element():
     torch = torch_cuda()
-    _say("config 2: 400^3 warped lattice, 1% of vertices jittered 0.8 (seed 0)")
+    _say("400^3 warped lattice, 1% of vertices jittered 0.8 (seed 0)")
     V, C = synth.warped_lattice(400, 400, 400, seed=0)
     assert C.shape[0] == 64_000_000 and V.shape[0] == 64_481_201
     v, m, st = hx.check(to_dev(torch, V), to_dev(torch, C), stats=True)
     torch.cuda.synchronize()
     v, m = v.cpu().numpy(), m.cpu().numpy()
-    _say(f"config 2 stats: {st}")
+    _say(f"400^3 lattice stats: {st}")
     assert st["n_subdivided"] > 0 and st["n_rounds"] == 1
-    _check_all(v, m, V, C, "config 2")
+    _check_all(v, m, V, C, "400^3 lattice")
     hist = np.bincount(v, minlength=4)
     assert hist[0] > 0 and hist[1] > 0
 
 
-def test_config3_precision_stress_every_element():
+def test_precision_stress_lattice_every_element():
     torch = torch_cuda()
-    _say("config 3: config 2 + 3.2M near-degenerate independent hexes (seed 1)")
+    _say("precision stress: 400^3 lattice + 3.2M near-degenerate independent hexes (seed 1)")
     V, C = synth.precision_stress()
     assert C.shape[0] == 67_200_000
     Vd, Cd = to_dev(torch, V), to_dev(torch, C)
@@ -55,21 +55,21 @@ def test_config3_precision_stress_every_element():
     v32, m32, st32 = hx.check(Vd, Cd, precision=hx.FP32_FILTER, stats=True)
     torch.cuda.synchronize()
     v64, m64, v32 = v64.cpu().numpy(), m64.cpu().numpy(), v32.cpu().numpy()
-    _say(f"config 3 stats: fp64 {st64} fp32 {st32}")
+    _say(f"precision stress stats: fp64 {st64} fp32 {st32}")
     assert (v32 == v64).all()
     assert st32["n_recheck"] >= 3_200_000
-    _check_all(v64, m64, V, C, "config 3")
+    _check_all(v64, m64, V, C, "precision stress")
 
 
-def test_config2_min_jacobian_every_element():
+def test_min_jacobian_400_cubed_lattice_every_element():
     import oracle
     torch = torch_cuda()
-    _say("config 2: min J bounds, rtol 1e-3, cap 6")
+    _say("400^3 lattice: min J bounds, rtol 1e-3, cap 6")
     V, C = synth.warped_lattice(400, 400, 400, seed=0)
     lo, hi, st, stats = hx.min_jacobian(to_dev(torch, V), to_dev(torch, C), rtol=1e-3, stats=True)
     torch.cuda.synchronize()
     lo, hi, st = lo.cpu().numpy(), hi.cpu().numpy(), st.cpu().numpy()
-    _say(f"config 2 min J stats: {stats}")
+    _say(f"400^3 lattice min J stats: {stats}")
     assert (st == hx.MINJ_CONVERGED).all()
     for a in range(0, C.shape[0], CHUNK):
         b = min(a + CHUNK, C.shape[0])

@@ -35,12 +35,12 @@ def _run(torch, P, conn=None, **kw):
     return v.cpu().numpy(), m.cpu().numpy(), st
 
 
-def test_config1_independent_hexes_full():
+def test_one_million_independent_hexes_full():
     torch = torch_cuda()
-    _say("config 1: 1,000,000 independent hexes, noise 0.35, seed 0")
+    _say("1,000,000 independent hexes, noise 0.35, seed 0")
     P = synth.independent_hexes(1_000_000, seed=0)
     v, m, st = _run(torch, P)
-    ref = assert_parity(v, m, P, label="config1")
+    ref = assert_parity(v, m, P, label="1M independent hexes")
     assert st["n_elements"] == 1_000_000
     # all 27 coefficients
     c = hx.coefficients(to_dev(torch, P)).cpu().numpy()
@@ -206,12 +206,12 @@ def _fp32_min_bound(points, conn=None):
     return 300.0 * U32 * oracle.scale(points, conn)
 
 
-@pytest.mark.parametrize("case", ["config1", "lattice", "stress", "tangled"])
+@pytest.mark.parametrize("case", ["independent", "lattice", "stress", "tangled"])
 def test_fp32_filter_verdicts_identical(case):
     torch = torch_cuda()
     _say(f"fp32 filter {case}")
     conn = None
-    if case == "config1":
+    if case == "independent":
         P = synth.independent_hexes(300000, seed=0)
     elif case == "lattice":
         P, conn = synth.warped_lattice(48, 40, 32, seed=2)

@@ -47,7 +47,7 @@ def values(E, pts):
     return c, s
 
 
-def test_config1_subset_matches_oracle(emul):
+def test_independent_hexes_subset_matches_oracle(emul):
     X = synth.independent_hexes(200000, seed=0)
     v, m, st = run_check(emul, X)
     r = oracle.check(X)
