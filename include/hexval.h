@@ -285,7 +285,8 @@ int hexval_server_submit(hexval_server_t* server, const hexval_request_t* reques
 int hexval_server_poll(hexval_server_t* server, uint64_t ticket, int* done, double* latency_ms);
 /* Blocks until ticket is done; returns its status. */
 int hexval_server_wait(hexval_server_t* server, uint64_t ticket, double* latency_ms);
-/* Waits for all requests, stops the scheduler, frees the server's memory. */
+/* Waits for all requests, stops the scheduler, frees the server's memory.
+ * No other call on this server may run during or after it. */
 int hexval_server_destroy(hexval_server_t* server);
 
 /* Message of the last non-OK status returned to the calling thread. */
