@@ -21,8 +21,9 @@
  *     UNDECIDED;
  *   - verdicts are those of the algorithm in EXACT arithmetic: every FP64
  *     (or FP32) sign decision is checked against a rigorous error bound and
- *     the few elements whose decisions cannot be certified are recomputed
- *     exactly on the host;
+ *     the few elements whose decisions cannot be certified are recomputed in
+ *     integer arithmetic (on the device when no exact subdivision is needed,
+ *     else on host threads);
  *   - min_coeff is the minimum of the 27 top-level coefficients (a lower
  *     bound of min J by the convex-hull property of Section 3.1), NaN for
  *     BAD_INPUT.
@@ -37,7 +38,10 @@
  *     n > 0, n < 0 or an option out of range returns HEXVAL_E_ARG without
  *     touching the GPU;
  *   - per-element input problems never fail a call: the element gets verdict
- *     HEXVAL_BAD_INPUT.
+ *     HEXVAL_BAD_INPUT;
+ *   - entry points may be called from several host threads at once: each
+ *     call takes its own workspace from a pool, and calls on one stream run
+ *     in order.
  */
 #ifndef HEXVAL_H
 #define HEXVAL_H
