@@ -195,6 +195,53 @@ def test_repeated_runs_are_bitwise_identical():
         assert (v == runs[0][0]).all() and np.array_equal(m, runs[0][1])
 
 
+def test_concurrent_calls_from_host_threads():
+    # four host threads, each on its own stream, call the library at the same
+    # time (FP64, FP32 filter, a tiny queue that forces deferred rounds, and
+    # min J): every result equals the same call made alone
+    import threading
+    torch = torch_cuda()
+    P0 = to_dev(torch, synth.independent_hexes(200000, noise=0.4, seed=31))
+    P1 = to_dev(torch, synth.independent_hexes(150000, noise=0.5, seed=32))
+    P2 = to_dev(torch, synth.independent_hexes(20000, noise=0.45, seed=9))
+    V, C = synth.warped_lattice(60, 50, 40, seed=33, jitter_fraction=0.05, jitter=0.5)
+    Vd, Cd = to_dev(torch, V), to_dev(torch, C)
+    jobs = [
+        lambda s: hx.check(P0, None, stream=s)[:2],
+        lambda s: hx.check(P1, None, precision=hx.FP32_FILTER, stream=s)[:2],
+        lambda s: hx.check(P2, None, queue_capacity=64, stream=s)[:2],
+        lambda s: hx.min_jacobian(Vd, Cd, rtol=1e-3, stream=s)[:2],
+    ]
+    alone = [job(torch.cuda.current_stream()) for job in jobs]
+    torch.cuda.synchronize()
+    alone = [tuple(x.cpu() for x in r) for r in alone]
+    for rep in range(3):
+        _say(f"concurrent calls, round {rep}")
+        out = [None] * len(jobs)
+        errors = []
+
+        def run(k):
+            try:
+                s = torch.cuda.Stream()
+                with torch.cuda.stream(s):
+                    r = jobs[k](s)
+                s.synchronize()
+                out[k] = tuple(x.cpu() for x in r)
+            except Exception as exc:   # reported below, in the test's thread
+                errors.append((k, exc))
+
+        threads = [threading.Thread(target=run, args=(k,)) for k in range(len(jobs))]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        assert not errors, errors
+        for k in range(len(jobs)):
+            for a, b in zip(out[k], alone[k]):
+                assert torch.equal(torch.nan_to_num(a, 7.0) if a.is_floating_point() else a,
+                                   torch.nan_to_num(b, 7.0) if b.is_floating_point() else b), (rep, k)
+
+
 # ------------------------------------------------------------ FP32 filter
 
 U32 = 2.0 ** -24
