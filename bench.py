@@ -93,33 +93,82 @@ def run_steps(hx, torch, pts, conn, steps, precision, stream):
     return time.perf_counter() - t0, stats, verdicts, mins
 
 
-def cpu_baseline(V, C, gpu_verdicts, target_s=12.0):
-    """The oracle (plain FP64 C, OpenMP over elements) on a bounded leading
-    sample of the same mesh; also checks the GPU verdicts of that sample."""
+def host_cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def timed_oracle_check(oracle, V, C, threads):
+    t0 = time.perf_counter()
+    ref = oracle.check(V, C, threads=threads)
+    return ref, time.perf_counter() - t0
+
+
+def cpu_baseline(V, C, gpu_verdicts, work, target_s=12.0):
+    """The oracle (plain FP64 C, OpenMP over elements, untuned) timed on the
+    host's cores: a bounded leading sample of the main mesh with all threads
+    and with one thread, the whole precision-stress mesh, a stated sample of
+    the batched workload's meshes, and the min-J oracle on a leading sample.
+    Every timed sample also checks the GPU results of the same elements."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     probe = min(C.shape[0], 1 << 20)
-    t0 = time.perf_counter()
-    oracle.check(V, C[:probe], threads=threads)
-    rate = probe / max(time.perf_counter() - t0, 1e-6)
+    _, dt = timed_oracle_check(oracle, V, C[:probe], threads)
+    rate = probe / max(dt, 1e-6)
     n = int(min(C.shape[0], max(probe, rate * target_s)))
-    t0 = time.perf_counter()
-    ref = oracle.check(V, C[:n], threads=threads)
-    dt = time.perf_counter() - t0
+    ref, dt = timed_oracle_check(oracle, V, C[:n], threads)
     mism = int((ref["verdict"] != gpu_verdicts[:n]).sum())
-    return {"value": n / dt, "unit": "hex/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} hexes of the same mesh ({dt:.1f} s)",
-            "verdict_mismatches_vs_gpu": mism}
+    # one thread, on a sample of about 3 s of its work
+    n1 = int(min(C.shape[0], max(1 << 16, 3.0 * rate / threads)))
+    ref1, dt1 = timed_oracle_check(oracle, V, C[:n1], 1)
+    out = {"value": n / dt, "unit": "hex/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {n} hexes of the same mesh ({dt:.1f} s)",
+           "per_core": n / dt / threads, "one_thread": n1 / dt1,
+           "one_thread_sample": f"first {n1} hexes of the same mesh ({dt1:.1f} s)",
+           "paper_one_core_context": "about 6e6 hex/s on one core of a 2016 laptop (context only)",
+           "cpu_model": host_cpu_model(), "nproc": os.cpu_count(),
+           "verdict_mismatches_vs_gpu": mism + int((ref1["verdict"] != gpu_verdicts[:n1]).sum())}
+    if "precision_stress" in work:
+        Vs, Cs, vs = work["precision_stress"]
+        ref, dt = timed_oracle_check(oracle, Vs, Cs, threads)
+        out["precision_stress"] = {"value": Cs.shape[0] / dt, "unit": "hex/s", "hexes": int(Cs.shape[0]),
+                                   "seconds": dt, "n_fragile_exact": int(ref["fragile"].size),
+                                   "verdict_mismatches_vs_gpu": int((ref["verdict"] != vs).sum())}
+    if "batched_sample" in work:
+        sample, label = work["batched_sample"]
+        nb, dt, mism_b = 0, 0.0, 0
+        for Vb, Cb, vb in sample:
+            ref, d = timed_oracle_check(oracle, Vb, Cb, threads)
+            nb += Cb.shape[0]
+            dt += d
+            mism_b += int((ref["verdict"] != vb).sum())
+        out["batched_sample"] = {"value": nb / dt, "unit": "hex/s", "hexes": nb, "seconds": dt,
+                                 "sample": label, "verdict_mismatches_vs_gpu": mism_b}
+    if "min_jacobian" in work:
+        m, rtol, lo, hi = work["min_jacobian"]
+        t0 = time.perf_counter()
+        ref = oracle.min_jacobian(V, C[:m], rtol=rtol, max_depth=6, threads=threads)
+        dt = time.perf_counter() - t0
+        disjoint = int(np.count_nonzero((lo > ref["hi"]) | (ref["lo"] > hi)))
+        out["min_jacobian"] = {"value": m / dt, "unit": "hex/s", "sample": f"first {m} hexes",
+                               "disjoint_intervals_vs_gpu": disjoint}
+    return out
 
 
-def fp32_leg(hx, torch, synth, steps, stream):
+def fp32_leg(hx, torch, synth, steps, stream, work):
     """Precision stress workload: the same lattice plus 5% near-degenerate,
     rescaled independent hexes; plain FP64 against the FP32 filter + FP64
     recheck on the same device-resident mesh."""
     V, C = synth.precision_stress(seed=0, seed_extra=1)
     pts = torch.from_numpy(V).to("cuda")
     conn = torch.from_numpy(C).to("cuda")
-    del V, C
     n = conn.shape[0]
     out = {"workload": "400^3 warped lattice + 5% near-degenerate hexes (one corner within 1e-7 "
                        "relative of flat, coordinates scaled by 10^U(-3,3))", "hexes": n}
@@ -134,6 +183,7 @@ def fp32_leg(hx, torch, synth, steps, stream):
                      "n_recheck": stats[-1]["n_recheck"], "n_exact": stats[-1]["n_exact"]}
     out["speedup_fp32_filter"] = out["fp32_filter"]["value"] / out["fp64"]["value"]
     out["verdicts_identical"] = bool(torch.equal(res["fp64"][0], res["fp32_filter"][0]))
+    work["precision_stress"] = (V, C, res["fp64"][0].cpu().numpy())
     # FP32 error of min_coeff against FP64, relative to each element's largest
     # FP64 coefficient (elements rechecked in FP64 have error 0)
     coeffs = hx.coefficients(pts, conn)
@@ -209,19 +259,26 @@ def serving_leg(hx, torch, synth, capacity_hex_s, n_req=2000, n_pool=32, seed=5)
     return out
 
 
-def batched_leg(hx, torch, synth, steps):
+def batched_leg(hx, torch, synth, steps, work):
     """Batched workload: 10,000 meshes, hex counts log-uniform in [1e2, 1e6],
     every vertex jittered by U(-a_m, a_m)^3 with a_m ~ U(0, 0.6), FP32 filter +
     FP64, depth cap 6: one persistent launch per step, against one
-    hexval_check_ex call per mesh."""
+    hexval_check_ex call per mesh.  The FP32-filter verdicts are compared with
+    the FP64 batch's and with the per-mesh calls' on every element; every
+    100th mesh and the largest are kept for the oracle in the CPU leg."""
     meshes = list(synth.batched_meshes_torch(10000, seed=4))
-    total = int(sum(C.shape[0] for _, C in meshes))
+    sizes = [C.shape[0] for _, C in meshes]
+    total = int(sum(sizes))
+    verts = int(sum(V.shape[0] for V, _ in meshes))
     vs = [torch.empty(C.shape[0], dtype=torch.uint8, device="cuda") for _, C in meshes]
     ms = [torch.empty(C.shape[0], dtype=torch.float64, device="cuda") for _, C in meshes]
     descs = [hx.make_mesh(V, C) for V, C in meshes]
     stream = torch.cuda.current_stream()
+    alg = algorithmic_bytes(total, verts)
     res = {"workload": "10,000 warped lattices, 1e2..1e6 hexes (log-uniform), all vertices jittered "
-                       "U(0,0.6) cell, FP32 filter + FP64, cap 6", "hexes": total, "meshes": len(meshes)}
+                       "U(0,0.6) cell, FP32 filter + FP64, cap 6", "hexes": total, "meshes": len(meshes),
+           "vertices": verts}
+    verdicts = {}
     for name, prec in (("fp32_filter", hx.FP32_FILTER), ("fp64", hx.FP64)):
         st = hx.hexval_stats_t()
         st.timing = 1
@@ -230,11 +287,17 @@ def batched_leg(hx, torch, synth, steps):
         hx.hexval_check_batched(args, opts)               # warm-up + tuning
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        first = []
         for _ in range(steps):
             hx.hexval_check_batched(args, opts)
+            first.append(st.ms_first_pass)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
+        verdicts[name] = torch.cat(vs)
+        gbps = alg / (float(np.mean(first)) * 1e-3) / 1e9
         res[name] = {"value": total / wall, "unit": "hex/s", "ms_per_step": 1e3 * wall,
+                     "first_pass": {"ms": float(np.mean(first)), "algorithmic_bytes": alg,
+                                    "achieved_GBps": gbps, "frac_of_8TBps": gbps / 8000.0},
                      "stats": st.as_dict()}
     # the same meshes one call at a time (FP32 filter)
     opts = hx.make_opts(precision=hx.FP32_FILTER, stream=stream)
@@ -244,16 +307,27 @@ def batched_leg(hx, torch, synth, steps):
         hx.hexval_check_ex(d, opts, v, m)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    per_mesh = torch.cat(vs)
     res["fp32_filter_one_call_per_mesh"] = {"value": total / wall, "unit": "hex/s", "ms_per_pass": 1e3 * wall}
     res["speedup_batched_vs_per_mesh"] = res["fp32_filter"]["value"] / res["fp32_filter_one_call_per_mesh"]["value"]
-    del meshes, vs, ms, descs
+    res["verdict_mismatches_fp32_filter_vs_fp64"] = int((verdicts["fp32_filter"] != verdicts["fp64"]).sum())
+    res["verdict_mismatches_batched_vs_per_mesh"] = int((verdicts["fp32_filter"] != per_mesh).sum())
+    res["verdicts_identical"] = (res["verdict_mismatches_fp32_filter_vs_fp64"] == 0
+                                 and res["verdict_mismatches_batched_vs_per_mesh"] == 0)
+    pick = sorted(set(range(0, len(meshes), 100)) | {int(np.argmax(sizes))})
+    offsets = np.cumsum([0] + sizes)
+    v_host = verdicts["fp32_filter"].cpu().numpy()
+    work["batched_sample"] = ([(meshes[k][0].cpu().numpy(), meshes[k][1].cpu().numpy(),
+                                v_host[offsets[k]:offsets[k + 1]]) for k in pick],
+                              f"every 100th of the 10,000 meshes and the largest ({len(pick)} meshes)")
+    del meshes, vs, ms, descs, verdicts, per_mesh
     return res
 
 
-def min_jacobian_leg(hx, torch, V, C, pts, conn, steps, stream, rtol=1e-3):
+def min_jacobian_leg(hx, torch, V, C, pts, conn, steps, stream, work, rtol=1e-3):
     """Certified bounds of min J (hexval_min_jacobian, rtol 1e-3, cap 6) on the
-    main mesh, inputs resident; the oracle timed on a leading sample."""
-    import oracle
+    main mesh, inputs resident; a leading sample is kept for the oracle in the
+    CPU leg."""
     n = conn.shape[0]
     lo = torch.empty(n, dtype=torch.float64, device="cuda")
     hi = torch.empty_like(lo)
@@ -271,11 +345,7 @@ def min_jacobian_leg(hx, torch, V, C, pts, conn, steps, stream, rtol=1e-3):
     wall = (time.perf_counter() - t0) / steps
     hist = np.bincount(status.cpu().numpy(), minlength=5)[:5].tolist()
     m = 1 << 22
-    t0 = time.perf_counter()
-    ref = oracle.min_jacobian(V, C[:m], rtol=rtol, max_depth=6)
-    t_cpu = time.perf_counter() - t0
-    lo_h, hi_h = lo[:m].cpu().numpy(), hi[:m].cpu().numpy()
-    disjoint = int(np.count_nonzero((lo_h > ref["hi"]) | (ref["lo"] > hi_h)))
+    work["min_jacobian"] = (m, rtol, lo[:m].cpu().numpy(), hi[:m].cpu().numpy())
     # first pass: connectivity, each vertex once, lo + hi + status (17 B/hex)
     alg = 32 * n + 24 * pts.shape[0] + 17 * n
     gbps = alg / (st.ms_first_pass * 1e-3) / 1e9
@@ -283,9 +353,7 @@ def min_jacobian_leg(hx, torch, V, C, pts, conn, steps, stream, rtol=1e-3):
             "value": n / wall, "unit": "hex/s", "ms_per_step": 1e3 * wall, "status_counts": hist,
             "first_pass": {"kernel": "k_minj_top_conn", "ms": st.ms_first_pass,
                            "algorithmic_bytes": alg, "achieved_GBps": gbps, "frac_of_8TBps": gbps / 8000.0},
-            "stats": st.as_dict(),
-            "oracle": {"value": m / t_cpu, "unit": "hex/s", "sample": f"first {m} hexes",
-                       "disjoint_intervals_vs_gpu": disjoint}}
+            "stats": st.as_dict()}
 
 
 def corner_test_leg(hx, torch, synth, steps, n_pool=16_000_000):
@@ -475,14 +543,16 @@ def main():
         "call_stats": stats[-1],
         "paper_context": "about 6e6 hex/s on one core of a 2016 laptop (the paper's serial C++), context only",
     }
+    work = {}   # host copies of GPU results for the oracle comparisons of the CPU leg
     if not args.no_extras:
         log("min J leg")
-        out["min_jacobian"] = min_jacobian_leg(hx, torch, V, C, pts, conn, max(3, args.steps // 4), stream)
+        out["min_jacobian"] = min_jacobian_leg(hx, torch, V, C, pts, conn, max(3, args.steps // 4), stream,
+                                               work)
         log(f"min J leg {out['min_jacobian']}")
         log("fp32 filter leg (precision stress workload)")
         del pts, conn
         torch.cuda.empty_cache()
-        out["fp32_filter_vs_fp64"] = fp32_leg(hx, torch, synth, max(5, args.steps // 2), stream)
+        out["fp32_filter_vs_fp64"] = fp32_leg(hx, torch, synth, max(5, args.steps // 2), stream, work)
         log(f"fp32 leg {out['fp32_filter_vs_fp64']}")
         torch.cuda.empty_cache()
         log("quad leg")
@@ -497,14 +567,14 @@ def main():
         out["exact_tier"] = exact_tier_leg(hx, torch, synth)
         log(f"exact tier leg {out['exact_tier']}")
         log("batched leg")
-        out["batched"] = batched_leg(hx, torch, synth, 3)
+        out["batched"] = batched_leg(hx, torch, synth, 3, work)
         log(f"batched leg {out['batched']}")
         torch.cuda.empty_cache()
         log("serving leg")
         out["serving"] = serving_leg(hx, torch, synth, value)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(V, C, v_host)
+        out["cpu_baseline"] = cpu_baseline(V, C, v_host, work)
         log(f"cpu baseline {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 
