@@ -5,6 +5,26 @@ import pytest
 import oracle
 
 
+_capture = None
+
+
+def set_capture_manager(cm):
+    """Called by conftest: pytest's capture manager, so that progress lines
+    can bypass output capture."""
+    global _capture
+    _capture = cm
+
+
+def say(msg):
+    """A progress line that reaches the terminal even while pytest captures
+    the test's output (long GPU tests print one at least every minute)."""
+    if _capture is not None:
+        with _capture.global_and_fixture_disabled():
+            print(msg, flush=True)
+    else:
+        print(msg, flush=True)
+
+
 def torch_cuda():
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():

@@ -11,3 +11,5 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
     config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
+    from tests import _gpu
+    _gpu.set_capture_manager(config.pluginmanager.getplugin("capturemanager"))

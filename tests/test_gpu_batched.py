@@ -1,24 +1,19 @@
 """GPU: the batched entry point (one persistent launch over many meshes)
 gives, for every mesh, the results of checking that mesh alone, and they
 agree with the oracle; the autotuned launch shape never changes results."""
-import sys
-
 import numpy as np
 import pytest
 
 import oracle
 from paper_1706_01613_amd import hexval as hx
 from paper_1706_01613_amd import synth
-from tests._gpu import assert_parity, normwise_error, torch_cuda
+from tests._gpu import say, assert_parity, normwise_error, torch_cuda
 
 U32 = 2.0 ** -24
 
 pytestmark = pytest.mark.gpu
 
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
+_say = say
 
 
 def _alone(torch, V, C, **kw):

@@ -2,8 +2,6 @@
 oracle.  Test-1 results are bit-exact (both sides take exact sign decisions);
 the quality agrees to 1e-12 (it lies in [-1, 1])."""
 import math
-import sys
-
 import numpy as np
 import pytest
 
@@ -11,15 +9,12 @@ import oracle
 from paper_1706_01613_amd import hexval as hx
 from paper_1706_01613_amd import synth
 from tests import _ref
-from tests._gpu import torch_cuda, to_dev
+from tests._gpu import say, torch_cuda, to_dev
 from tests.test_oracle_pins import CUBE, _twisted
 
 pytestmark = pytest.mark.gpu
 
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
+_say = say
 
 
 def _gpu(torch, P, conn=None, **kw):

@@ -5,23 +5,18 @@ Every element is compared with the oracle (the oracle takes a few seconds
 for 64M hexes on the host's cores): verdicts bit-exact, min_coeff within
 1e-12 of the element's largest coefficient.
 """
-import sys
-
 import numpy as np
 import pytest
 
 from paper_1706_01613_amd import hexval as hx
 from paper_1706_01613_amd import synth
-from tests._gpu import assert_parity, torch_cuda, to_dev
+from tests._gpu import say, assert_parity, torch_cuda, to_dev
 
 pytestmark = pytest.mark.gpu
 
 CHUNK = 1 << 22
 
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
+_say = say
 
 
 def _check_all(v, m, V, C, label):

@@ -9,8 +9,6 @@ is well away from the stopping rule's threshold.  Closed forms and a dense
 grid pin the GPU intervals directly.
 """
 import math
-import sys
-
 import numpy as np
 import pytest
 
@@ -18,17 +16,14 @@ import oracle
 from paper_1706_01613_amd import hexval as hx
 from paper_1706_01613_amd import synth
 from tests import _ref
-from tests._gpu import torch_cuda, to_dev
+from tests._gpu import say, torch_cuda, to_dev
 from tests.test_oracle_pins import CUBE, _prism, _twisted
 
 pytestmark = pytest.mark.gpu
 
 U = 2.0 ** -53
 
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
+_say = say
 
 
 def _gpu(torch, P, conn=None, **kw):

@@ -5,8 +5,6 @@ Bezier coefficients and min_coeff must agree to 1e-12 relative to the
 element's largest coefficient.
 """
 import math
-import sys
-
 import numpy as np
 import pytest
 
@@ -14,16 +12,13 @@ import oracle
 from paper_1706_01613_amd import hexval as hx
 from paper_1706_01613_amd import synth
 from tests import _ref
-from tests._gpu import assert_parity, torch_cuda, to_dev
+from tests._gpu import say, assert_parity, torch_cuda, to_dev
 
 pytestmark = pytest.mark.gpu
 
 CUBE = synth.CUBE
 
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
+_say = say
 
 
 def _run(torch, P, conn=None, **kw):

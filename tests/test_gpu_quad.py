@@ -1,21 +1,16 @@
 """GPU: linear quadrangle validity (Section 2.1) against the oracle: verdicts
 bit-exact, min J (the smallest corner value) to 1e-14 of S^2."""
-import sys
-
 import numpy as np
 import pytest
 
 import oracle
 from paper_1706_01613_amd import hexval as hx
 from paper_1706_01613_amd import synth
-from tests._gpu import torch_cuda, to_dev
+from tests._gpu import say, torch_cuda, to_dev
 
 pytestmark = pytest.mark.gpu
 
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
+_say = say
 
 
 def _gpu(torch, P, conn=None, **kw):

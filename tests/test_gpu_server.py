@@ -2,21 +2,17 @@
 the same alone and in the mix (bitwise: the arithmetic of an element never
 depends on what else runs), host-uploaded requests match device-resident
 ones, and admission respects the HBM budget."""
-import sys
-
 import numpy as np
 import pytest
 
 from paper_1706_01613_amd import hexval as hx
 from paper_1706_01613_amd import loadgen, synth
-from tests._gpu import assert_parity, torch_cuda
+from tests._gpu import assert_parity, say, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
 
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
+_say = say
 
 
 def _pool(torch, n, seed, lo=3.0, hi=5.3):
