@@ -169,6 +169,26 @@ int hexval_check_batched(const hexval_mesh_t* meshes, int32_t n_meshes,
  */
 int hexval_coefficients(const hexval_mesh_t* mesh, void* stream, double* coeffs);
 
+/*
+ * hexval_check_noalloc: hexval_check_ex for callers that cannot allocate
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  It allocates no device or pinned host memory: its
+ * subdivision store, check lists, counters and exact-tier staging live in a
+ * fixed array of the library (about 38 MiB of device memory per GPU it runs
+ * on, held until the process ends) and in fixed host arrays.  The caller
+ * passes inputs and outputs as for hexval_check_ex; the results are the same.
+ * Limits: max_depth <= 8 and queue_capacity <= 2^17 (else HEXVAL_E_ARG);
+ * devices 0..15; timing statistics are not recorded (stats->ms_* stay 0).
+ * Elements beyond the fixed capacities are checked in later rounds.  The
+ * host exact tier, reached only for elements whose exact decision the device
+ * tier cannot settle, uses ordinary host memory.  Every call on one GPU uses
+ * that GPU's single copy of the array and leaves its contents behind: calls
+ * that overlap on one GPU (from several host threads or on several streams)
+ * race and must be serialised by the caller.
+ */
+int hexval_check_noalloc(const hexval_mesh_t* mesh, const hexval_opts_t* opts,
+                         uint8_t* verdicts, double* min_coeffs);
+
 /* ---- corner-only test and corner quality ------------------------------------
  * hexval_corner_test: Test 1 of the comparison in Section 7 (the volumes of
  * the 8 corner tetrahedra, i.e. the 8 corner values of J = the corner

@@ -129,6 +129,7 @@ constexpr uint64_t kExactCap = 1ull << 16;
 
 Workspace::~Workspace()
 {
+    if (borrowed) return;
     int prev = -1;
     hipGetDevice(&prev);
     hipSetDevice(device);
@@ -531,7 +532,11 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     WorkspaceGuard wg;
     if (!fixed && (rc = acquire_workspace(dev, &wg.w))) return rc;
     Workspace& w = fixed ? *fixed : *wg.w;
-    if (fixed) node_cap = list_cap = 0;   // a fixed workspace keeps its capacities
+    if (fixed) {
+        // a fixed workspace keeps its capacities; queue_capacity may only narrow the store
+        node_cap = o.queue_capacity ? std::min<uint64_t>((uint64_t)o.queue_capacity, fixed->node_cap) : 0;
+        list_cap = 0;
+    }
     const int64_t max_tiles = count_tiles(need_tune ? 64 : choice.block);
     if ((rc = w.ensure(node_cap, list_cap, batched ? n_meshes : 1, batched ? max_tiles : 1))) return rc;
     QueueDev q = w.queue();
@@ -572,7 +577,7 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         }
         return HEXVAL_OK;
     };
-    const bool timing = st && st->timing;
+    const bool timing = st && st->timing && w.ev[0];   // workspaces without events do not time
     const int xcds = 8;
     auto first_args = [&]() {
         TopArgs ta{};
@@ -1001,6 +1006,134 @@ int run_coefficients(const hexval_mesh_t* mesh, void* stream, double* coeffs)
     return HEXVAL_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free check
+// hexval_check_noalloc runs on buffers carved from `scratch`, a fixed device
+// array of this library, and on fixed host arrays: the call allocates no
+// device or pinned host memory.  Capacities: a subdivision store of 2^17
+// sub-boxes (it holds one element's tree whose ambiguous region is a surface
+// up to depth 8, the deepest such a call accepts), a recheck/deferred list of
+// 2^17 entries and exact-tier staging for 2^13 elements; elements past these
+// are checked in later rounds, as with any workspace.  Every call on a device
+// uses that device's one copy: concurrent calls on one device race.
+
+constexpr uint64_t kNaNodes = 1ull << 17;
+constexpr uint64_t kNaList = 1ull << 17;
+constexpr uint64_t kNaExact = 1ull << 13;
+constexpr int kNaMaxDepth = 8;
+constexpr int kNaMaxDevices = 16;
+
+constexpr uint64_t na_align(uint64_t x) { return (x + 255) & ~255ull; }
+constexpr uint64_t kNaOffCnt = 0;
+constexpr uint64_t kNaOffNodes = na_align(kNaOffCnt + sizeof(Counters));
+constexpr uint64_t kNaOffSubElem = na_align(kNaOffNodes + kNaNodes * sizeof(Node));
+constexpr uint64_t kNaOffSubMesh = na_align(kNaOffSubElem + kNaNodes * sizeof(int64_t));
+constexpr uint64_t kNaOffSubFlags = na_align(kNaOffSubMesh + kNaNodes * sizeof(int32_t));
+constexpr uint64_t kNaOffListElem = na_align(kNaOffSubFlags + kNaNodes * sizeof(uint32_t));
+constexpr uint64_t kNaOffListMesh = na_align(kNaOffListElem + kNaList * sizeof(int64_t));
+constexpr uint64_t kNaOffExactElem = na_align(kNaOffListMesh + kNaList * sizeof(int32_t));
+constexpr uint64_t kNaOffExactMesh = na_align(kNaOffExactElem + kNaExact * sizeof(int64_t));
+constexpr uint64_t kNaOffExactPts = na_align(kNaOffExactMesh + kNaExact * sizeof(int32_t));
+constexpr uint64_t kNaOffExactV = na_align(kNaOffExactPts + kNaExact * 24 * sizeof(double));
+constexpr uint64_t kScratchBytes = na_align(kNaOffExactV + kNaExact);
+
+// One copy per device (loaded with the library's code object on that
+// device).  Host code must not use this name as an address: it is a host-side
+// stand-in; the device address comes from hipGetSymbolAddress below.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Host staging of the allocation-free path (counters read back, exact-tier
+// points and verdicts), one per device.
+struct NoAllocHost {
+    Counters cnt;
+    double pts[kNaExact * 24];
+    uint8_t v[kNaExact];
+};
+static NoAllocHost g_na_host[kNaMaxDevices];
+
+struct NoAllocDevice {
+    std::once_flag once;
+    int rc = HEXVAL_OK;
+    char msg[256] = {0};
+    Workspace ws;
+};
+static NoAllocDevice g_na[kNaMaxDevices];
+
+// Set-up on the first call on device dev (that device current): the address
+// of this device's scratch array, and a workspace whose buffers point into it.
+static int noalloc_workspace(int dev, Workspace** out)
+{
+    if (dev >= kNaMaxDevices)
+        return fail(HEXVAL_E_ARG, "hexval_check_noalloc supports devices 0..%d, not %d", kNaMaxDevices - 1, dev);
+    NoAllocDevice& d = g_na[dev];
+    std::call_once(d.once, [&] {
+        unsigned char* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            hipGetLastError();
+            d.rc = HEXVAL_E_HIP;
+            snprintf(d.msg, sizeof d.msg, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev,
+                     hipGetErrorString(e));
+            return;
+        }
+        Workspace& w = d.ws;
+        NoAllocHost& h = g_na_host[dev];
+        w.borrowed = true;
+        w.device = dev;
+        w.cnt = reinterpret_cast<Counters*>(p + kNaOffCnt);
+        w.nodes = reinterpret_cast<Node*>(p + kNaOffNodes);
+        w.sub_elem = reinterpret_cast<int64_t*>(p + kNaOffSubElem);
+        w.sub_mesh = reinterpret_cast<int32_t*>(p + kNaOffSubMesh);
+        w.sub_flags = reinterpret_cast<uint32_t*>(p + kNaOffSubFlags);
+        w.list_elem = reinterpret_cast<int64_t*>(p + kNaOffListElem);
+        w.list_mesh = reinterpret_cast<int32_t*>(p + kNaOffListMesh);
+        w.exact_elem = reinterpret_cast<int64_t*>(p + kNaOffExactElem);
+        w.exact_mesh = reinterpret_cast<int32_t*>(p + kNaOffExactMesh);
+        w.exact_pts = reinterpret_cast<double*>(p + kNaOffExactPts);
+        w.exact_v = p + kNaOffExactV;
+        w.hcnt = &h.cnt;
+        w.h_exact_pts = h.pts;
+        w.h_exact_v = h.v;
+        w.node_cap = kNaNodes;
+        w.list_cap = kNaList;
+        w.exact_cap = kNaExact;
+        w.mesh_cap = 1;   // single-mesh calls only: the mesh and tile tables stay unused
+        w.tile_cap = 1;
+    });
+    if (d.rc) return fail(d.rc, "%s", d.msg);
+    *out = &d.ws;
+    return HEXVAL_OK;
+}
+
+int run_check_noalloc(const hexval_mesh_t* mesh, const hexval_opts_t* opts, uint8_t* verdicts, double* mins)
+{
+    if (!mesh) return fail(HEXVAL_E_ARG, "mesh is NULL");
+    hexval_opts_t o;
+    if (opts) o = *opts;
+    else default_opts(&o);
+    int rc = check_opts(&o);
+    if (rc) return rc;
+    if (o.max_depth > kNaMaxDepth)
+        return fail(HEXVAL_E_ARG, "hexval_check_noalloc: max_depth %d exceeds %d, the deepest its fixed store of "
+                    "%llu sub-boxes is sized for", o.max_depth, kNaMaxDepth, (unsigned long long)kNaNodes);
+    if ((uint64_t)o.queue_capacity > kNaNodes)
+        return fail(HEXVAL_E_ARG, "hexval_check_noalloc: queue_capacity %lld exceeds its fixed store of %llu sub-boxes",
+                    (long long)o.queue_capacity, (unsigned long long)kNaNodes);
+    if ((rc = check_mesh(mesh, verdicts, o.validate_indices, 0))) return rc;
+    if (mesh->n == 0) {
+        if (o.stats) {
+            const int timing = o.stats->timing;
+            memset(o.stats, 0, sizeof *o.stats);
+            o.stats->timing = timing;
+        }
+        return HEXVAL_OK;
+    }
+    int dev;
+    if ((rc = current_device(&dev, nullptr))) return rc;
+    Workspace* w = nullptr;
+    if ((rc = noalloc_workspace(dev, &w))) return rc;
+    return run_check_ws(mesh, 1, false, &o, &verdicts, &mins, w, false);
+}
+
 }  // namespace hexval
 
 // ---------------------------------------------------------------- C ABI
@@ -1052,6 +1185,12 @@ int hexval_check_batched(const hexval_mesh_t* meshes, int32_t n_meshes, const he
 int hexval_coefficients(const hexval_mesh_t* mesh, void* stream, double* coeffs)
 {
     return run_coefficients(mesh, stream, coeffs);
+}
+
+int hexval_check_noalloc(const hexval_mesh_t* mesh, const hexval_opts_t* opts, uint8_t* verdicts,
+                         double* min_coeffs)
+{
+    return run_check_noalloc(mesh, opts, verdicts, min_coeffs);
 }
 
 const char* hexval_last_error(void) { return last_error(); }

@@ -21,6 +21,7 @@ int check_opts(const hexval_opts_t* o);
 // workspace from start to finish.
 struct Workspace {
     int device = 0;
+    bool borrowed = false;   // buffers owned elsewhere (never freed here)
     uint64_t node_cap = 0, exact_cap = 0, list_cap = 0, mesh_cap = 0, tile_cap = 0;
     Node* nodes = nullptr;
     int64_t* sub_elem = nullptr;

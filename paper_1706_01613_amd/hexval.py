@@ -77,6 +77,8 @@ def lib():
             "hexval_check_batched": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t), I32,
                                                     ctypes.POINTER(hexval_opts_t), P, P]),
             "hexval_coefficients": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t), P, P]),
+            "hexval_check_noalloc": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t),
+                                                    ctypes.POINTER(hexval_opts_t), P, P]),
             "hexval_quad_check": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t),
                                                  ctypes.POINTER(hexval_opts_t), P, P]),
             "hexval_corner_test": (ctypes.c_int, [ctypes.POINTER(hexval_mesh_t),
@@ -164,6 +166,12 @@ def hexval_check_ex(mesh, opts, verdicts, min_coeffs=None):
     """C: hexval_check_ex (mesh: hexval_mesh_t, opts: hexval_opts_t or None)."""
     return _check(lib().hexval_check_ex(ctypes.byref(mesh), ctypes.byref(opts) if opts else None,
                                         _addr(verdicts), _addr(min_coeffs)))
+
+
+def hexval_check_noalloc(mesh, opts, verdicts, min_coeffs=None):
+    """C: hexval_check_noalloc (mesh: hexval_mesh_t, opts: hexval_opts_t or None)."""
+    return _check(lib().hexval_check_noalloc(ctypes.byref(mesh), ctypes.byref(opts) if opts else None,
+                                             _addr(verdicts), _addr(min_coeffs)))
 
 
 class BatchArgs:

@@ -81,6 +81,17 @@ def test_argument_errors_without_gpu():
     empty = hx.hexval_mesh_t(None, 0, None, 0)
     assert L.hexval_corner_test(ctypes.byref(empty), None, None, None) == hx.OK
     assert L.hexval_min_jacobian(ctypes.byref(empty), None, 1e-3, None, None, None) == hx.OK
+    # the allocation-free check: its own limits are argument errors
+    assert L.hexval_check_noalloc(None, None, 32, None) == hx.E_ARG
+    assert L.hexval_check_noalloc(ctypes.byref(empty), None, None, None) == hx.OK
+    for field, value in [("max_depth", 9), ("queue_capacity", (1 << 17) + 1), ("max_depth", 21)]:
+        o = hx.hexval_opts_default()
+        setattr(o, field, value)
+        assert L.hexval_check_noalloc(ctypes.byref(mesh), ctypes.byref(o), 32, None) == hx.E_ARG, field
+    o = hx.hexval_opts_default()
+    o.max_depth = 9
+    L.hexval_check_noalloc(ctypes.byref(mesh), ctypes.byref(o), 32, None)
+    assert "hexval_check_noalloc" in hx.hexval_last_error()
     h = ctypes.c_void_p()
     assert L.hexval_server_create(None, 0, 1, ctypes.byref(h)) == hx.E_ARG
     assert L.hexval_server_create(None, 1 << 30, 0, ctypes.byref(h)) == hx.E_ARG
@@ -97,6 +108,7 @@ def test_no_device_reports_hip_error():
     assert "device" in hx.hexval_last_error()
     mesh = hx.hexval_mesh_t(16, 0, None, 4)
     assert L.hexval_min_jacobian(ctypes.byref(mesh), None, 1e-3, 32, 48, None) == hx.E_HIP
+    assert L.hexval_check_noalloc(ctypes.byref(mesh), None, 32, None) == hx.E_HIP
     h = ctypes.c_void_p()
     assert L.hexval_server_create(None, 1 << 34, 2, ctypes.byref(h)) == hx.E_HIP
 
