@@ -93,6 +93,41 @@ def run_steps(hx, torch, pts, conn, steps, precision, stream):
     return time.perf_counter() - t0, stats, verdicts, mins
 
 
+def machine_ceilings(torch):
+    """Achievable rates of this GPU from kernels of known work
+    (libhexval_calib.so): a read-only stream over 8 GiB, a 2 GiB copy, and
+    FP64 FMA chains on every lane (with the shader clock during them)."""
+    import ctypes
+    L = ctypes.CDLL(os.path.join(ROOT, "paper_1706_01613_amd", "libhexval_calib.so"))
+    P, I64, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    L.hexval_calib_read.argtypes = [P, I64, I, P]
+    L.hexval_calib_copy.argtypes = [P, P, I64, I, P]
+    L.hexval_calib_fp64.argtypes = [I64, I, P, P, P]
+    ms = ctypes.c_float()
+    out = {}
+    nb = 8 << 30
+    buf = torch.ones(nb, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    assert L.hexval_calib_read(buf.data_ptr(), nb, 10, ctypes.byref(ms)) == 0
+    out["hbm_read_GBps"] = nb / (ms.value * 1e-3) / 1e9
+    del buf
+    nb = 2 << 30
+    src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    assert L.hexval_calib_copy(dst.data_ptr(), src.data_ptr(), nb, 10, ctypes.byref(ms)) == 0
+    out["hbm_copy_GBps"] = 2 * nb / (ms.value * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    flops, mhz = ctypes.c_double(), ctypes.c_double()
+    assert L.hexval_calib_fp64(1 << 14, 5, ctypes.byref(ms), ctypes.byref(flops), ctypes.byref(mhz)) == 0
+    out["fp64_fma_TFLOPs"] = flops.value / (ms.value * 1e-3) / 1e12
+    out["shader_clock_MHz_during_fp64"] = mhz.value
+    out["what"] = ("read-only 16-byte stream over 8 GiB; copy of 2 GiB (read + write bytes); 8 independent "
+                   "FP64 FMA chains per lane on 8 blocks of 256 per CU")
+    return out
+
+
 def host_cpu_model():
     """The host CPU's model name (from /proc/cpuinfo), or None."""
     try:
@@ -513,6 +548,9 @@ def main():
         f"({achieved:.0f} GB/s algorithmic), verdicts {hist}, stats {stats[-1]}")
     if args.copy_calib:
         copy_calibration(torch)
+    log("machine ceilings")
+    ceilings = machine_ceilings(torch)
+    log(f"machine ceilings {ceilings}")
 
     out = {
         "metric": METRIC,
@@ -537,7 +575,9 @@ def main():
                      "algorithmic_bytes_per_launch": alg,
                      "avg_launch_ms": float(first.mean()),
                      "valu": {"achieved": valu_ops, "peak": VALU_PEAK_OPS, "unit": "FP64 lane-ops/s",
-                              "frac": valu_ops / VALU_PEAK_OPS, "ops_per_hex": VALU_OPS_PER_HEX}},
+                              "frac": valu_ops / VALU_PEAK_OPS, "ops_per_hex": VALU_OPS_PER_HEX},
+                     "frac_of_measured_read_ceiling": achieved / ceilings["hbm_read_GBps"]},
+        "machine_ceilings": ceilings,
         "verdicts": {"invalid": hist[0], "valid": hist[1], "undecided": hist[2],
                      "bad_input": hist[3]},
         "call_stats": stats[-1],

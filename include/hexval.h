@@ -26,7 +26,12 @@
  *     else on host threads);
  *   - min_coeff is the minimum of the 27 top-level coefficients (a lower
  *     bound of min J by the convex-hull property of Section 3.1), NaN for
- *     BAD_INPUT.
+ *     BAD_INPUT.  Computed in FP64 it is within 256 u M^ of the exact
+ *     minimum (u = 2^-53, M^ = 6 S_xi S_eta S_zeta, S_d the largest |component|
+ *     of the element's four edge vectors along direction d); under
+ *     HEXVAL_FP32_FILTER an element the FP32 pass decides returns the FP32
+ *     minimum widened to double, within 256 u32 M^ (u32 = 2^-24), and an
+ *     element rechecked in FP64 returns the FP64 value.
  *
  * Conventions for every entry point:
  *   - array pointers named "device" are device pointers (hipMalloc'd memory or
@@ -75,7 +80,10 @@ enum {
     HEXVAL_FP64 = 0,        /* every element in FP64 */
     HEXVAL_FP32_FILTER = 1  /* FP32 pass with a forward error bound per value and
                                coefficient; elements it cannot certify, and every
-                               subdivision, are recomputed in FP64 */
+                               subdivision, are recomputed in FP64.  Verdicts are
+                               those of HEXVAL_FP64; min_coeff of an element the
+                               FP32 pass decides is FP32-accurate (within
+                               256 u32 M^, see min_coeff above) */
 };
 
 /* A mesh.  points: device, [n_points,3] float64 when connectivity != NULL,
@@ -108,6 +116,10 @@ typedef struct {
                               the host (exact subdivision or a coordinate span
                               over 78 bits) */
     int64_t grid_blocks;   /* first-pass grid used */
+    int32_t walk_layers;   /* layers per column tile of the first pass (0: plain
+                              tiles) */
+    int32_t reserved;
+    int64_t walk_stride;   /* stack stride found for the column walk (0: none) */
 } hexval_stats_t;
 
 /* Options.  Use hexval_opts_default() and change fields. */
@@ -125,6 +137,14 @@ typedef struct {
                                  to a multiple of 8) */
     void* stream;             /* hipStream_t to run on; NULL = the null stream */
     hexval_stats_t* stats;    /* optional output */
+    int32_t walk_layers;      /* single mesh with trusted connectivity: the first
+                                 pass checks columns of elements stacked with the
+                                 stride it finds (element e + s has as corners 0..3
+                                 the corners 4..7 of element e), loading each
+                                 shared face once; this many layers per column
+                                 tile.  0 = tuned (default), -1 = plain tiles,
+                                 1..64 = this many.  Results never depend on it */
+    int32_t reserved;         /* must be 0 */
 } hexval_opts_t;
 
 /* Fills *opts with the defaults above. */

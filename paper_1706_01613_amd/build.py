@@ -19,6 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhexval.so")
 EMUL = os.path.join(HERE, "libhexval_emul.so")
 LOADGEN = os.path.join(HERE, "libhexval_loadgen.so")
+CALIB = os.path.join(HERE, "libhexval_calib.so")
 
 SOURCES = ["hexval_kernels.hip", "hexval_runtime.hip", "hexval_exact.cpp", "hexval_server.cpp"]
 
@@ -78,6 +79,14 @@ def build(verbose=False, jobs=4):
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         os.replace(out, LOADGEN)
+        # machine ceilings (HBM read, copy, FP64 FMA) for the benchmark
+        out = CALIB + ".tmp"
+        cmd = [cc, *HIPCC_FLAGS, "-I", INCLUDE, "-shared", "-x", "hip",
+               os.path.join(CSRC, "hexval_calib.hip"), "-o", out]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        os.replace(out, CALIB)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
     return LIB

@@ -56,7 +56,10 @@ struct alignas(256) Counters {
     unsigned long long n_exact;       // elements listed for the exact tier
     unsigned long long n_deferred;    // elements deferred to a later pass
     unsigned long long n_list;        // entries in the FP64 (re)check list
-    unsigned long long pad[4];
+    unsigned long long walk_code;     // stack stride of a single mesh: limit - stride, 0 = none
+    unsigned long long walk_break;    // 2^62 - first layer whose column 0 breaks the stack, 0 = none
+    unsigned long long n_rechecked;   // FP32 filter: elements redone in FP64 inside the pass
+    unsigned long long pad[1];
     // first-pass tile counters, one per XCD chunk, each on a 256-byte line
     unsigned long long tile_next[8 * 32];
 };

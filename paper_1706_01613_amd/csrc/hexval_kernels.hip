@@ -589,6 +589,243 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     push_flush(pb, sub_list(a.q), a.q, m, nullptr);
 }
 
+// ------------------------------------------------------------ column walk
+//
+// In a structured mesh stacked layer by layer, element e + s (s elements per
+// layer) has as its bottom face (corners 0..3) the top face (corners 4..7) of
+// element e.  The walking first passes give each lane a column of elements
+// e, e + s, e + 2s, ...: a lane loads the 4 new corners of each element and
+// takes the other 4 from LDS, where it left the previous element's top face,
+// which halves the vertex loads and the distinct cache lines per element and
+// keeps a vertex plane on chip between the two layers that share it.  The
+// carried face is a cache keyed by vertex index: a lane compares the
+// element's bottom corner ids with the ids it holds and loads all 8 corners
+// when they differ, so any connectivity gives the same result, and only the
+// speed depends on the stride found.
+
+
+// Finds the smallest e in [1, limit) whose corners 0..3 are corners 4..7 of
+// element 0, and records it as limit - e in c->walk_code (atomicMax, so the
+// smallest e wins; 0 = none).  Threads stop once a smaller e is recorded.
+__global__ __launch_bounds__(256) void k_walk_detect(const int32_t* conn, int64_t limit, Counters* c)
+{
+    const int t0 = conn[4], t1 = conn[5], t2 = conn[6], t3 = conn[7];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < limit; e += stride) {
+        if ((int64_t)load_relaxed(&c->walk_code) > limit - e) return;
+        const int32_t* b = conn + 8 * e;
+        if (b[0] == t0 && b[1] == t1 && b[2] == t2 && b[3] == t3)
+            atomicMax(&c->walk_code, (unsigned long long)(limit - e));
+    }
+}
+
+constexpr unsigned long long kWalkBreakBase = 1ull << 62;
+
+// With the stride s found, the first layer l >= 1 whose element l s does not
+// sit on element (l - 1) s (its corners 0..3 are not the other's 4..7), as
+// 2^62 - l in c->walk_break (atomicMax: the first such layer wins; 0 =
+// none).  The walk covers the layers before it; a mesh whose stacked part is
+// followed by unrelated elements checks those with plain tiles.
+__global__ __launch_bounds__(256) void k_walk_extent(const int32_t* conn, int64_t n, int64_t limit, Counters* c)
+{
+    const unsigned long long code = c->walk_code;
+    const int64_t s = code ? limit - (int64_t)code : 0;
+    if (s < kWalkMinStride || s >= n) return;
+    const int64_t nl = (n + s - 1) / s;
+    for (int64_t l = 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < nl; l += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t* lo = conn + 8 * ((l - 1) * s);
+        const int32_t* up = conn + 8 * (l * s);
+        if (up[0] != lo[4] || up[1] != lo[5] || up[2] != lo[6] || up[3] != lo[7])
+            atomicMax(&c->walk_break, kWalkBreakBase - (unsigned long long)l);
+    }
+}
+
+// Tiles of a walking pass: blockDim.x consecutive columns of a layer times
+// `layers` consecutive layers; walk tile t covers column block t % ncb of
+// the layer block t / ncb, over the layers before the first break.  The
+// elements after them are the tail, in plain tiles of blockDim.x elements
+// numbered after the walk tiles.  Without a usable stride the whole mesh is
+// the tail.
+struct WalkShape {
+    int64_t s;        // elements per layer
+    int32_t ncb;      // column blocks per layer
+    int32_t nl;       // layers walked
+    int32_t layers;   // layers per tile
+    int64_t n_walk;   // walk tiles
+    int64_t tail;     // first element of the tail
+    int64_t n_tiles;
+    __device__ WalkShape(int64_t n, const Counters* c, int64_t limit, int walk_layers)
+    {
+        const unsigned long long code = c->walk_code, brk = c->walk_break;
+        s = code ? limit - (int64_t)code : 0;
+        layers = walk_layers;
+        if (s < kWalkMinStride || s >= n || layers < 1) {
+            s = n;
+            nl = 0;
+            layers = 1;
+        } else {
+            const int64_t all = (n + s - 1) / s;
+            nl = (int32_t)(brk ? (int64_t)(kWalkBreakBase - brk) : all);
+        }
+        ncb = (int32_t)((s + blockDim.x - 1) / blockDim.x);
+        n_walk = (int64_t)ncb * ((nl + layers - 1) / layers);
+        tail = (int64_t)nl * s < n ? (int64_t)nl * s : n;
+        n_tiles = n_walk + (n - tail + blockDim.x - 1) / blockDim.x;
+    }
+};
+
+// The block's position in a walking pass (block-uniform): the element of
+// its column 0 in the current layer, the columns of its block that exist,
+// and the layers left in the current tile.  Lane l checks element base + l.
+struct WalkPos {
+    int64_t base;
+    int64_t cols;
+    int32_t left;
+    // First layer of tile t.
+    __device__ void start(const WalkShape& ws, int64_t t)
+    {
+        if (t >= ws.n_walk) {         // a plain tile of the tail
+            base = ws.tail + (t - ws.n_walk) * blockDim.x;
+            cols = blockDim.x;
+            left = 1;
+            return;
+        }
+        const int32_t lb = (int32_t)(t / ws.ncb);
+        const int64_t c0 = (t - (int64_t)lb * ws.ncb) * blockDim.x;
+        const int32_t l0 = lb * ws.layers;
+        cols = ws.s - c0;
+        base = (int64_t)l0 * ws.s + c0;
+        left = ws.nl - l0 < ws.layers ? ws.nl - l0 : ws.layers;
+    }
+};
+
+// conn_prefetch_loop over the steps (tile, layer) of a walking pass: the
+// connectivity rows of a lane's next element go to LDS before the current
+// element's vertex loads.  body(e, active, idx) as in conn_prefetch_loop.
+template <typename Body>
+__device__ __forceinline__ void walk_prefetch_loop(const int32_t* conn, int64_t n, const WalkShape& ws,
+                                                   TileSched& ts, int4* stage, Body body)
+{
+    const int wave_base = threadIdx.x & ~63;
+    auto prefetch = [&](int64_t e) {
+        e = e < n ? e : n - 1;        // past the end: a valid row, ignored
+        const int* src = conn + 8 * e;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            __builtin_amdgcn_global_load_lds(src + 4 * h, (lds_ptr)&stage[h * 256 + wave_base], 16, 0, 0);
+    };
+    WalkPos pos;
+    int64_t t = ts.next_tile();
+    if (t >= 0) {
+        pos.start(ws, t);
+        prefetch(pos.base + threadIdx.x);
+    }
+    wait_vmem();
+    while (t >= 0) {
+        int idx[8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int4 c = stage[h * 256 + threadIdx.x];
+            idx[4 * h] = c.x;
+            idx[4 * h + 1] = c.y;
+            idx[4 * h + 2] = c.z;
+            idx[4 * h + 3] = c.w;
+        }
+        const int64_t e = pos.base + threadIdx.x;
+        const bool active = (int64_t)threadIdx.x < pos.cols && e < n;
+        // the next step: the layer above in the same tile, else the next tile
+        if (pos.left > 1) {
+            pos.base += ws.s;
+            --pos.left;
+        } else {
+            t = ts.next_tile();
+            if (t >= 0) pos.start(ws, t);
+        }
+        wait_lds();                    // the slots are free: every lane has read its row
+        issue_priority();
+        prefetch(t >= 0 ? pos.base + threadIdx.x : e);
+        body(e, active, idx);
+    }
+}
+
+// This lane's carried face in LDS: the ids of the 4 vertices it holds and
+// their coordinates, coordinate-major per lane so that a wave's accesses are
+// conflict-free.
+struct CarrySlots {
+    int id[4 * 256];
+    double xyz[12 * 256];
+};
+
+// Vertex loads of one element with the carried face: corners 4..7 always,
+// corners 0..3 only when this lane's slots do not hold them.  Returns
+// whether they do.
+__device__ __forceinline__ bool carry_issue(const double* points, const int idx[8], const CarrySlots& cs, V3 p[8])
+{
+    const int l = threadIdx.x;
+    const bool hit = idx[0] == cs.id[l] && idx[1] == cs.id[256 + l] && idx[2] == cs.id[512 + l] &&
+                     idx[3] == cs.id[768 + l];
+#pragma unroll
+    for (int k = 4; k < 8; ++k) {
+        const auto* v = global(points) + 3 * (int64_t)idx[k];
+        p[k] = {v[0], v[1], v[2]};
+    }
+    if (!hit) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const auto* v = global(points) + 3 * (int64_t)idx[k];
+            p[k] = {v[0], v[1], v[2]};
+        }
+    }
+    return hit;
+}
+
+// After the loads have landed: corners 0..3 from the slots on a hit, and
+// corners 4..7 left there for the element above.
+__device__ __forceinline__ void carry_finish(const int idx[8], bool hit, CarrySlots& cs, V3 p[8])
+{
+    const int l = threadIdx.x;
+    if (hit) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            p[k] = {cs.xyz[(3 * k) * 256 + l], cs.xyz[(3 * k + 1) * 256 + l], cs.xyz[(3 * k + 2) * 256 + l]};
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        cs.xyz[(3 * k) * 256 + l] = p[k + 4].x;
+        cs.xyz[(3 * k + 1) * 256 + l] = p[k + 4].y;
+        cs.xyz[(3 * k + 2) * 256 + l] = p[k + 4].z;
+        cs.id[k * 256 + l] = idx[k + 4];
+    }
+}
+
+// No vertex held yet (before the first element; indices are >= 0).
+__device__ __forceinline__ void carry_clear(CarrySlots& cs)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cs.id[k * 256 + threadIdx.x] = -1;
+}
+
+// k_top_f64_conn with the column walk.
+template <bool EDGES>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_top_f64_walk(TopArgs a)
+{
+    __shared__ int4 stage[2 * 256];
+    __shared__ CarrySlots cs;
+    HX_PUSH_STORAGE;
+    const MeshDev& m = a.mesh;
+    const WalkShape ws(m.n, a.q.cnt, a.walk_limit, a.walk_layers);
+    TileSched ts(ws.n_tiles, a.xcds, a.q.cnt);
+    carry_clear(cs);
+    walk_prefetch_loop(m.conn, m.n, ws, ts, stage, [&](int64_t e, bool active, const int* idx) {
+        V3 p[8];
+        const bool hit = carry_issue(m.points, idx, cs, p);
+        wait_loads();                  // vertices and the next rows have landed
+        carry_finish(idx, hit, cs, p);
+        finish_element<EDGES>(m, 0, e, active, p, false, a.q, a.max_depth, pb, nullptr);
+    });
+    push_flush(pb, sub_list(a.q), a.q, m, nullptr);
+}
+
 // k_top_f64_range for a batch whose meshes all have trusted connectivity,
 // through batch_prefetch_loop.
 template <bool EDGES>
@@ -704,6 +941,46 @@ __global__ __launch_bounds__(256) void k_filter_f32_conn(TopArgs a)
         filter_finish(m, 0, e, active, p, false, a.q, pb, nullptr);
     });
     push_flush(pb, recheck_list(a.q), a.q, m, nullptr);
+}
+
+// k_filter_f32_conn with the column walk, and the FP64 recheck in the same
+// pass: the carried face's LDS already limits the block count to what 168
+// registers allow, so the elements the FP32 pass cannot decide are redone in
+// FP64 from the corners still in registers (as finish_element decides them,
+// subdivision list included) instead of being listed and gathered again.
+template <bool EDGES>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_filter_f32_walk(TopArgs a)
+{
+    __shared__ int4 stage[2 * 256];
+    __shared__ CarrySlots cs;
+    HX_PUSH_STORAGE;
+    const MeshDev& m = a.mesh;
+    const WalkShape ws(m.n, a.q.cnt, a.walk_limit, a.walk_layers);
+    TileSched ts(ws.n_tiles, a.xcds, a.q.cnt);
+    carry_clear(cs);
+    walk_prefetch_loop(m.conn, m.n, ws, ts, stage, [&](int64_t e, bool active, const int* idx) {
+        V3 p[8];
+        const bool hit = carry_issue(m.points, idx, cs, p);
+        wait_loads();
+        carry_finish(idx, hit, cs, p);
+        int st = -1;
+        float mn = 0.0f;
+        if (active) {
+            const LeanT<float> r = element_lean_t<float>(p, false);
+            st = filter_state(r);
+            mn = r.min27;
+        }
+        const bool recheck = active && st < 0;
+        if (active && !recheck) {
+            *global(m.verdict + e) = (uint8_t)st;
+            if (m.min_coeff) *global(m.min_coeff + e) = (double)mn;
+        }
+        if (ballot(recheck)) {
+            wave_count(&a.q.cnt->n_rechecked, recheck);
+            finish_element<EDGES>(m, 0, e, recheck, p, false, a.q, a.max_depth, pb, nullptr);
+        }
+    });
+    push_flush(pb, sub_list(a.q), a.q, m, nullptr);
 }
 
 // k_filter_f32_range for a batch whose meshes all have trusted
@@ -1154,6 +1431,24 @@ __global__ __launch_bounds__(256) void k_minj_top_conn(MinjArgs a)
         V3 p[8];
         gather8(m.points, idx, p);
         wait_loads();
+        minj_element(a, e, active, p, false);
+    });
+}
+
+// k_minj_top_conn with the column walk.
+__global__ __launch_bounds__(256) void k_minj_top_walk(MinjArgs a)
+{
+    __shared__ int4 stage[2 * 256];
+    __shared__ CarrySlots cs;
+    const MeshDev& m = a.mesh;
+    const WalkShape ws(m.n, a.q.cnt, a.walk_limit, a.walk_layers);
+    TileSched ts(ws.n_tiles, a.xcds, a.q.cnt);
+    carry_clear(cs);
+    walk_prefetch_loop(m.conn, m.n, ws, ts, stage, [&](int64_t e, bool active, const int* idx) {
+        V3 p[8];
+        const bool hit = carry_issue(m.points, idx, cs, p);
+        wait_loads();
+        carry_finish(idx, hit, cs, p);
         minj_element(a, e, active, p, false);
     });
 }
@@ -1730,10 +2025,12 @@ void launch_top_range(const TopArgs& a, bool batched, int grid, int block, hipSt
 #define HX_TOP(E, G) HX_LAUNCH((k_top_f64_range<false, E, G>), grid, block, s, a)
     if (edges) {
         if (g == kGatherPoints) HX_TOP(true, kGatherPoints);
+        else if (g == kGatherConn && a.walk_layers) HX_LAUNCH((k_top_f64_walk<true>), grid, block, s, a);
         else if (g == kGatherConn) HX_LAUNCH((k_top_f64_conn<true>), grid, block, s, a);
         else HX_TOP(true, kGatherChecked);
     } else {
         if (g == kGatherPoints) HX_TOP(false, kGatherPoints);
+        else if (g == kGatherConn && a.walk_layers) HX_LAUNCH((k_top_f64_walk<false>), grid, block, s, a);
         else if (g == kGatherConn) HX_LAUNCH((k_top_f64_conn<false>), grid, block, s, a);
         else HX_TOP(false, kGatherChecked);
     }
@@ -1749,6 +2046,8 @@ void launch_filter_range(const TopArgs& a, bool batched, int grid, int block, hi
     }
     if (!a.mesh.conn) HX_LAUNCH((k_filter_f32_range<false, kGatherPoints>), grid, block, s, a);
     else if (a.mesh.validate) HX_LAUNCH((k_filter_f32_range<false, kGatherChecked>), grid, block, s, a);
+    else if (a.walk_layers && a.max_depth == 0) HX_LAUNCH(k_filter_f32_walk<true>, grid, block, s, a);
+    else if (a.walk_layers) HX_LAUNCH(k_filter_f32_walk<false>, grid, block, s, a);
     else HX_LAUNCH(k_filter_f32_conn, grid, block, s, a);
 }
 
@@ -1765,6 +2064,12 @@ void launch_level(const LevelArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_lev
 void launch_roots(const RootArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_roots, grid, 256, s, a); }
 void launch_fold(const FoldArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_fold, grid, 256, s, a); }
 void launch_reset(Counters* c, hipStream_t s) { HX_LAUNCH(k_reset, 1, 64, s, c); }
+void launch_walk_detect(const int32_t* conn, int64_t n, int64_t limit, Counters* c, hipStream_t s)
+{
+    const int64_t g = (limit + 255) / 256;
+    HX_LAUNCH(k_walk_detect, g < 1024 ? g : 1024, 256, s, conn, limit, c);
+    HX_LAUNCH(k_walk_extent, 64, 256, s, conn, n, limit, c);
+}
 void launch_tile_table(const MeshDev* meshes, int n_meshes, int tile, int32_t* tile_mesh, hipStream_t s)
 {
     HX_LAUNCH(k_tile_table, n_meshes < 4096 ? n_meshes : 4096, 256, s, meshes, n_meshes, tile, tile_mesh);
@@ -1795,7 +2100,8 @@ void launch_quad_gather(const CornerArgs& a, int64_t n, double* out, hipStream_t
 }
 void launch_minj_top(const MinjArgs& a, int grid, hipStream_t s)
 {
-    if (!a.in_list && a.mesh.conn && !a.mesh.validate) HX_LAUNCH(k_minj_top_conn, grid, 256, s, a);
+    if (!a.in_list && a.mesh.conn && !a.mesh.validate && a.walk_layers) HX_LAUNCH(k_minj_top_walk, grid, 256, s, a);
+    else if (!a.in_list && a.mesh.conn && !a.mesh.validate) HX_LAUNCH(k_minj_top_conn, grid, 256, s, a);
     else HX_LAUNCH(k_minj_top, grid, 256, s, a);
 }
 void launch_minj_roots(const MinjArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_minj_roots, grid, 256, s, a); }

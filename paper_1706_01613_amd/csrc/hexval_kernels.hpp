@@ -17,7 +17,8 @@ struct TopArgs {
     int32_t max_depth;
     int32_t xcds;                         // tile chunks (1 or 8)
     int32_t batch_conn;                   // batched: every mesh with tiles has trusted connectivity
-    int32_t pad;
+    int32_t walk_layers;                  // single trusted mesh: layers per column tile (0: no walk)
+    int64_t walk_limit;                   // elements searched for the stack stride (see k_walk_detect)
 };
 
 struct LevelArgs {
@@ -86,6 +87,8 @@ struct MinjArgs {
     int32_t level;
     int32_t max_depth;
     int32_t xcds;
+    int32_t walk_layers;      // first round over a trusted mesh: layers per column tile (0: no walk)
+    int64_t walk_limit;       // elements searched for the stack stride
 };
 
 // Corner-only test and corner quality (hexval_corner_test).
@@ -110,6 +113,17 @@ void launch_minj_level(const MinjArgs& a, int grid, hipStream_t s);
 void launch_minj_fold(const MinjArgs& a, int grid, hipStream_t s);
 
 void launch_top_range(const TopArgs& a, bool batched, int grid, int block, hipStream_t s);
+// Column walk of the first pass over a single mesh with trusted
+// connectivity: the stack stride is searched among the first kWalkSearch
+// elements, and the layers it holds for counted (launch_walk_detect, after
+// launch_reset; the walking pass reads both from the Counters); a tile spans
+// kWalkLayers layers.
+constexpr int64_t kWalkSearch = 1ll << 22;
+constexpr int kWalkLayers = 16;
+// Smallest stride walked (below it a column tile would leave too many lanes
+// idle).
+constexpr int64_t kWalkMinStride = 4096;
+void launch_walk_detect(const int32_t* conn, int64_t n, int64_t limit, Counters* c, hipStream_t s);
 void launch_filter_range(const TopArgs& a, bool batched, int grid, int block, hipStream_t s);
 void launch_top_list(const TopArgs& a, bool batched, int grid, int block, hipStream_t s);
 void launch_level(const LevelArgs& a, int grid, hipStream_t s);

@@ -67,6 +67,20 @@ HEXVAL_HD double triple(V3 a, V3 b, V3 c)
     return fma(a.z, z, fma(a.y, y, a.x * x));
 }
 
+// a x b with fused components (the cross product inside triple()), and
+// c . X with the fused dot product of triple(): dot(c, cross(a, b)) is
+// triple(c, a, b) bit for bit.
+HEXVAL_HD V3 cross(V3 a, V3 b)
+{
+    return {fma(a.y, b.z, -(a.z * b.y)), fma(a.z, b.x, -(a.x * b.z)), fma(a.x, b.y, -(a.y * b.x))};
+}
+HEXVAL_HD double dot(V3 c, V3 x) { return fma(c.z, x.z, fma(c.y, x.y, c.x * x.x)); }
+// c . x + d . y as one fused chain of six products.
+HEXVAL_HD double dot2(V3 c, V3 x, V3 d, V3 y)
+{
+    return fma(d.z, y.z, fma(d.y, y.y, fma(d.x, y.x, fma(c.z, x.z, fma(c.y, x.y, c.x * x.x)))));
+}
+
 HEXVAL_HD double amax(double m, V3 v)
 {
     return fmax(m, fmax(fabs(v.x), fmax(fabs(v.y), fabs(v.z))));
@@ -84,14 +98,26 @@ HEXVAL_HD double amax(double m, V3 v)
 //   8 b_27 = sum_12 (4 v_e) - 5 sum_8 v_c
 //
 // Error bounds (u = 2^-53, S_d = largest |component| of the four edge vectors
-// of direction d, M = 6 S_xi S_eta S_zeta, |J| <= M everywhere):
+// of direction d, M = 6 S_xi S_eta S_zeta, |J| <= M everywhere; first-order
+// terms, the second-order ones are below 1e-14 of them):
 //   corner value:   |c^ - c| <= ((1+u)^3 (1+g5) - 1) M       <= 8.01 u M
-//   4 x edge value: operands B, C are pair sums (error g2 of |b0|+|b1|, the
-//                   permanent of the magnitudes is 4M):    <= 40.01 u M
-//   so values J carry <= 10.01 u M < kTauValue u M^.
-//   2 b_e: 40.01 + 2*8.01 + 4 + 4   (u M)                  -> b_e  <= 32.01 u M
-//   4 b_f: 3*40.01 + 192.04 + 28                            -> b_f  <= 85.01 u M
-//   8 b_27: 5*88.01 + 672.13 + 88                           -> b_27 <= 150.02 u M
+//   2 b_e, xi- and eta-edges: a cross component (|X| <= 2 S S') carries
+//     <= 3u S S'; the six-product fused chain adds u (6+5+...+1) 2 = 42u to
+//     the 6 * 3u = 18u of its operands (units S_xi S_eta S_zeta):
+//     60u = 10 u M                                          -> b_e <= 5 u M
+//   2 b_e, zeta-edges: the triple of pair sums carries 132u = 22 u M, the
+//     corner pair sum 2 * 8.01 + 2, the subtraction 6 (|2 b_e| <= 6 M):
+//     46.02 u M                                             -> b_e <= 23.01 u M
+//   4 J at an edge midpoint, (2 b_e) + (v_p + v_q): 10 + 18.02 + 4 on xi- and
+//     eta-edges; on zeta-edges the pair sum's error cancels (the same rounded
+//     sum is subtracted and added back): 22 + 6 + 4.  So values J carry
+//     <= 8.01 u M < kTauValue u M^.
+//   4 b_f = sum_4 (2 b_e) - sum_4 v_c: edge terms 2 * 10 + 2 * 46.02, their
+//     summation 32, the corner sum 2 * 18.02 + 4, the subtraction 28
+//     (|4 b_f| <= 28 M): 212.08 u M                         -> b_f <= 53.02 u M
+//   8 b_27 = sum_12 (2 b_e) - 2 sum_8 v_c: edge terms 8 * 10 + 4 * 46.02,
+//     their summation 136, the corners 2 * 88.08, the final fma 88
+//     (|8 b_27| <= 88 M): 664.24 u M                       -> b_27 <= 83.03 u M
 //   so top-level coefficients carry < kTauCoeff u M^.
 //   A de Casteljau halving along one axis adds <= g2 max|b| <= 22.01 u M
 //   (|b| <= 11 M: absolute row sums of Table 3 are at most 11), three axes per
@@ -123,67 +149,66 @@ HEXVAL_HD void element_values(const V3 p[8], ElementValues& r)
     const V3 c00 = sub3(p[4], p[0]), c10 = sub3(p[5], p[1]);
     const V3 c01 = sub3(p[7], p[3]), c11 = sub3(p[6], p[2]);
 
-    r.c[0] = triple(a00, b00, c00);  // (0,0,0)
-    r.c[1] = triple(a00, b10, c10);  // (1,0,0)
-    r.c[2] = triple(a10, b10, c11);  // (1,1,0)
-    r.c[3] = triple(a10, b00, c01);  // (0,1,0)
-    r.c[4] = triple(a01, b01, c00);  // (0,0,1)
-    r.c[5] = triple(a01, b11, c10);  // (1,0,1)
-    r.c[6] = triple(a11, b11, c11);  // (1,1,1)
-    r.c[7] = triple(a11, b01, c01);  // (0,1,1)
+    // Corner (i,j,k): J = c_ij . X(i,j,k) with X(i,j,k) = a_jk x b_ik.
+    const V3 X0 = cross(a00, b00), X1 = cross(a00, b10), X2 = cross(a10, b10), X3 = cross(a10, b00);
+    const V3 X4 = cross(a01, b01), X5 = cross(a01, b11), X6 = cross(a11, b11), X7 = cross(a11, b01);
+    double* c = r.c;
+    c[0] = dot(c00, X0);  // (0,0,0)
+    c[1] = dot(c10, X1);  // (1,0,0)
+    c[2] = dot(c11, X2);  // (1,1,0)
+    c[3] = dot(c01, X3);  // (0,1,0)
+    c[4] = dot(c00, X4);  // (0,0,1)
+    c[5] = dot(c10, X5);  // (1,0,1)
+    c[6] = dot(c11, X6);  // (1,1,1)
+    c[7] = dot(c01, X7);  // (0,1,1)
 
-    const V3 B0 = add3(b00, b10), B1 = add3(b01, b11);     // 2 x_eta,  xi=1/2
-    const V3 C0 = add3(c00, c10), C1 = add3(c01, c11);     // 2 x_zeta, xi=1/2
-    const V3 A0 = add3(a00, a10), A1 = add3(a01, a11);     // 2 x_xi,   eta=1/2
-    const V3 Cq0 = add3(c00, c01), Cq1 = add3(c10, c11);   // 2 x_zeta, eta=1/2
+    // Edge midpoints.  4 J at the midpoint of a xi-edge p-q is C . (X_p + X_q)
+    // with C the pair sum of the zeta-edges at p and q (linearity of the
+    // cross product in its second factor), and of an eta-edge likewise with
+    // the first factor; expanding C leaves v_p + v_q plus the two mixed
+    // terms, so 2 b_e = 4 v_e - (v_p + v_q) = c_q . X_p + c_p . X_q (c_p the
+    // zeta-edge at p) without cancellation.  On a zeta-edge the two factors
+    // both change, and 2 b_e = triple(A', B', c) - (v_p + v_q) with the pair
+    // sums A', B' across it.  Corner pairs of the edges 9..20 (0-based):
+    // (0,1)(1,2)(2,3)(3,0)(0,4)(1,5)(2,6)(3,7)(4,5)(5,6)(6,7)(7,4).
+    double* e = r.e;
+    e[0] = dot2(c10, X0, c00, X1);    //  9 (1/2,0,0)
+    e[1] = dot2(c11, X1, c10, X2);    // 10 (1,1/2,0)
+    e[2] = dot2(c11, X3, c01, X2);    // 11 (1/2,1,0)
+    e[3] = dot2(c01, X0, c00, X3);    // 12 (0,1/2,0)
+    e[8] = dot2(c10, X4, c00, X5);    // 17 (1/2,0,1)
+    e[9] = dot2(c11, X5, c10, X6);    // 18 (1,1/2,1)
+    e[10] = dot2(c11, X7, c01, X6);   // 19 (1/2,1,1)
+    e[11] = dot2(c01, X4, c00, X7);   // 20 (0,1/2,1)
     const V3 Aq0 = add3(a00, a01), Aq1 = add3(a10, a11);   // 2 x_xi,   zeta=1/2
     const V3 Bq0 = add3(b00, b01), Bq1 = add3(b10, b11);   // 2 x_eta,  zeta=1/2
-
-    r.d[0] = triple(a00, B0, C0);     //  9 (1/2,0,0)
-    r.d[1] = triple(A0, b10, Cq1);    // 10 (1,1/2,0)
-    r.d[2] = triple(a10, B0, C1);     // 11 (1/2,1,0)
-    r.d[3] = triple(A0, b00, Cq0);    // 12 (0,1/2,0)
-    r.d[4] = triple(Aq0, Bq0, c00);   // 13 (0,0,1/2)
-    r.d[5] = triple(Aq0, Bq1, c10);   // 14 (1,0,1/2)
-    r.d[6] = triple(Aq1, Bq1, c11);   // 15 (1,1,1/2)
-    r.d[7] = triple(Aq1, Bq0, c01);   // 16 (0,1,1/2)
-    r.d[8] = triple(a01, B1, C0);     // 17 (1/2,0,1)
-    r.d[9] = triple(A1, b11, Cq1);    // 18 (1,1/2,1)
-    r.d[10] = triple(a11, B1, C1);    // 19 (1/2,1,1)
-    r.d[11] = triple(A1, b01, Cq0);   // 20 (0,1/2,1)
-
-    // Table 3.  Corner pairs of the edges 9..20: (1,2)(2,3)(3,4)(4,1)(1,5)(2,6)
-    // (3,7)(4,8)(5,6)(6,7)(7,8)(8,5), 0-based below.
-    const double* c = r.c;
     const double s01 = c[0] + c[1], s12 = c[1] + c[2], s23 = c[2] + c[3], s30 = c[3] + c[0];
     const double s04 = c[0] + c[4], s15 = c[1] + c[5], s26 = c[2] + c[6], s37 = c[3] + c[7];
     const double s45 = c[4] + c[5], s56 = c[5] + c[6], s67 = c[6] + c[7], s74 = c[7] + c[4];
-    const double* d = r.d;
-    r.e[0] = d[0] - s01;
-    r.e[1] = d[1] - s12;
-    r.e[2] = d[2] - s23;
-    r.e[3] = d[3] - s30;
-    r.e[4] = d[4] - s04;
-    r.e[5] = d[5] - s15;
-    r.e[6] = d[6] - s26;
-    r.e[7] = d[7] - s37;
-    r.e[8] = d[8] - s45;
-    r.e[9] = d[9] - s56;
-    r.e[10] = d[10] - s67;
-    r.e[11] = d[11] - s74;
+    e[4] = triple(Aq0, Bq0, c00) - s04;   // 13 (0,0,1/2)
+    e[5] = triple(Aq0, Bq1, c10) - s15;   // 14 (1,0,1/2)
+    e[6] = triple(Aq1, Bq1, c11) - s26;   // 15 (1,1,1/2)
+    e[7] = triple(Aq1, Bq0, c01) - s37;   // 16 (0,1,1/2)
+    // 4 J at the edge midpoints (the step-2 values)
+    const double sp[12] = {s01, s12, s23, s30, s04, s15, s26, s37, s45, s56, s67, s74};
+#pragma unroll
+    for (int k = 0; k < 12; ++k) r.d[k] = e[k] + sp[k];
+
+    // Table 3 with the 2 b_e above: each corner of a face lies on two of its
+    // edges and each corner of the element on three, so
+    //   4 b_f = sum_4 (4 v_e) - 3 sum_4 v_c = sum_4 (2 b_e) - sum_4 v_c,
+    //   8 b_27 = sum_12 (4 v_e) - 5 sum_8 v_c = sum_12 (2 b_e) - 2 sum_8 v_c.
     // Faces 21..26 = zeta=0, eta=0, xi=1, eta=1, xi=0, zeta=1: their corners
     // and edges (Fig. 3 numbering).
+    const double ez0 = (e[0] + e[2]) + (e[1] + e[3]), ez1 = (e[8] + e[10]) + (e[9] + e[11]);
     const double cz0 = s01 + s23, cz1 = s45 + s67;
-    const double dz0 = (d[0] + d[2]) + (d[1] + d[3]);
-    const double dz1 = (d[8] + d[10]) + (d[9] + d[11]);
-    const double dvert = (d[4] + d[5]) + (d[6] + d[7]);
-    r.f[0] = fma(-3.0, cz0, dz0);                                   // 21: 1234 | 9 10 11 12
-    r.f[1] = fma(-3.0, s01 + s45, (d[0] + d[8]) + (d[4] + d[5]));   // 22: 1256 | 9 13 14 17
-    r.f[2] = fma(-3.0, s12 + s56, (d[1] + d[9]) + (d[5] + d[6]));   // 23: 2367 | 10 14 15 18
-    r.f[3] = fma(-3.0, s23 + s67, (d[2] + d[10]) + (d[6] + d[7]));  // 24: 3478 | 11 15 16 19
-    r.f[4] = fma(-3.0, s30 + s74, (d[3] + d[11]) + (d[4] + d[7]));  // 25: 1458 | 12 13 16 20
-    r.f[5] = fma(-3.0, cz1, dz1);                                   // 26: 5678 | 17 18 19 20
-    r.z = fma(-5.0, cz0 + cz1, (dz0 + dz1) + dvert);                // 27
+    r.f[0] = ez0 - cz0;                                          // 21: 1234 | 9 10 11 12
+    r.f[1] = ((e[0] + e[8]) + (e[4] + e[5])) - (s01 + s45);      // 22: 1256 | 9 13 14 17
+    r.f[2] = ((e[1] + e[9]) + (e[5] + e[6])) - (s12 + s56);      // 23: 2367 | 10 14 15 18
+    r.f[3] = ((e[2] + e[10]) + (e[6] + e[7])) - (s23 + s67);     // 24: 3478 | 11 15 16 19
+    r.f[4] = ((e[3] + e[11]) + (e[4] + e[7])) - (s30 + s74);     // 25: 1458 | 12 13 16 20
+    r.f[5] = ez1 - cz1;                                          // 26: 5678 | 17 18 19 20
+    r.z = fma(-2.0, cz0 + cz1, (ez0 + ez1) + ((e[4] + e[5]) + (e[6] + e[7])));   // 27
 
     double sx = 0.0, sy = 0.0, sz = 0.0;
     sx = amax(amax(amax(amax(sx, a00), a10), a01), a11);
@@ -330,6 +355,24 @@ HEXVAL_HD T triple_t(W3<T> a, W3<T> b, W3<T> c)
 }
 
 template <typename T>
+HEXVAL_HD W3<T> cross_t(W3<T> a, W3<T> b)
+{
+    return {fma(a.y, b.z, -(a.z * b.y)), fma(a.z, b.x, -(a.x * b.z)), fma(a.x, b.y, -(a.y * b.x))};
+}
+
+template <typename T>
+HEXVAL_HD T dot_t(W3<T> c, W3<T> x)
+{
+    return fma(c.z, x.z, fma(c.y, x.y, c.x * x.x));
+}
+
+template <typename T>
+HEXVAL_HD T dot2_t(W3<T> c, W3<T> x, W3<T> d, W3<T> y)
+{
+    return fma(d.z, y.z, fma(d.y, y.y, fma(d.x, y.x, fma(c.z, x.z, fma(c.y, x.y, c.x * x.x)))));
+}
+
+template <typename T>
 HEXVAL_HD T amax_t(T m, W3<T> v)
 {
     return fmax(m, fmax(fabs(v.x), fmax(fabs(v.y), fabs(v.z))));
@@ -351,55 +394,80 @@ template <> struct Guard<float> {
 template <typename T>
 HEXVAL_HD LeanT<T> element_lean_t(const V3 p[8], bool check_edges)
 {
-    const W3<T> a00 = edge_t<T>(p[1], p[0]), a10 = edge_t<T>(p[2], p[3]);
-    const W3<T> a01 = edge_t<T>(p[5], p[4]), a11 = edge_t<T>(p[6], p[7]);
-    const W3<T> b00 = edge_t<T>(p[3], p[0]), b10 = edge_t<T>(p[2], p[1]);
-    const W3<T> b01 = edge_t<T>(p[7], p[4]), b11 = edge_t<T>(p[6], p[5]);
+    // zeta-edges first: their pair sums need the edges of both faces, which
+    // then need only stay live for their own face
     const W3<T> c00 = edge_t<T>(p[4], p[0]), c10 = edge_t<T>(p[5], p[1]);
     const W3<T> c01 = edge_t<T>(p[7], p[3]), c11 = edge_t<T>(p[6], p[2]);
-    const T sx = fmax(fmax(amax_t(fabs(a00.x), a10), amax_t(fabs(a00.y), a01)), amax_t(fabs(a00.z), a11));
-    const T sy = fmax(fmax(amax_t(fabs(b00.x), b10), amax_t(fabs(b00.y), b01)), amax_t(fabs(b00.z), b11));
     const T sz = fmax(fmax(amax_t(fabs(c00.x), c10), amax_t(fabs(c00.y), c01)), amax_t(fabs(c00.z), c11));
-
-    const T c0 = triple_t(a00, b00, c00), c1 = triple_t(a00, b10, c10);
-    const T c2 = triple_t(a10, b10, c11), c3 = triple_t(a10, b00, c01);
-    const T c4 = triple_t(a01, b01, c00), c5 = triple_t(a01, b11, c10);
-    const T c6 = triple_t(a11, b11, c11), c7 = triple_t(a11, b01, c01);
+    const W3<T> a00 = edge_t<T>(p[1], p[0]), a10 = edge_t<T>(p[2], p[3]);
+    const W3<T> a01 = edge_t<T>(p[5], p[4]), a11 = edge_t<T>(p[6], p[7]);
+    const T sx = fmax(fmax(amax_t(fabs(a00.x), a10), amax_t(fabs(a00.y), a01)), amax_t(fabs(a00.z), a11));
+    const W3<T> b00 = edge_t<T>(p[3], p[0]), b10 = edge_t<T>(p[2], p[1]);
+    const W3<T> b01 = edge_t<T>(p[7], p[4]), b11 = edge_t<T>(p[6], p[5]);
+    const T sy = fmax(fmax(amax_t(fabs(b00.x), b10), amax_t(fabs(b00.y), b01)), amax_t(fabs(b00.z), b11));
+    T t4, t5, t6, t7;
+    {
+        const W3<T> Aq0 = add_t(a00, a01), Aq1 = add_t(a10, a11);
+        const W3<T> Bq0 = add_t(b00, b01), Bq1 = add_t(b10, b11);
+        t4 = triple_t(Aq0, Bq0, c00);
+        t5 = triple_t(Aq0, Bq1, c10);
+        t6 = triple_t(Aq1, Bq1, c11);
+        t7 = triple_t(Aq1, Bq0, c01);
+    }
+    // Corners and the 2 b_e of the xi- and eta-edges of the bottom face
+    // (k = 0) and the top face (k = 1), from the corner cross products as in
+    // element_values; each face's crosses are consumed as they are formed.
+    T c0, c1, c2, c3, e0, e1, e2, e3;
+    {
+        const W3<T> X0 = cross_t(a00, b00), X1 = cross_t(a00, b10);
+        c0 = dot_t(c00, X0);
+        c1 = dot_t(c10, X1);
+        e0 = dot2_t(c10, X0, c00, X1);
+        const W3<T> X3 = cross_t(a10, b00);
+        c3 = dot_t(c01, X3);
+        e3 = dot2_t(c01, X0, c00, X3);
+        const W3<T> X2 = cross_t(a10, b10);
+        c2 = dot_t(c11, X2);
+        e1 = dot2_t(c11, X1, c10, X2);
+        e2 = dot2_t(c11, X3, c01, X2);
+    }
+    T c4, c5, c6, c7, e8, e9, e10, e11;
+    {
+        const W3<T> X4 = cross_t(a01, b01), X5 = cross_t(a01, b11);
+        c4 = dot_t(c00, X4);
+        c5 = dot_t(c10, X5);
+        e8 = dot2_t(c10, X4, c00, X5);
+        const W3<T> X7 = cross_t(a11, b01);
+        c7 = dot_t(c01, X7);
+        e11 = dot2_t(c01, X4, c00, X7);
+        const W3<T> X6 = cross_t(a11, b11);
+        c6 = dot_t(c11, X6);
+        e9 = dot2_t(c11, X5, c10, X6);
+        e10 = dot2_t(c11, X7, c01, X6);
+    }
     const T s01 = c0 + c1, s12 = c1 + c2, s23 = c2 + c3, s30 = c3 + c0;
     const T s04 = c0 + c4, s15 = c1 + c5, s26 = c2 + c6, s37 = c3 + c7;
     const T s45 = c4 + c5, s56 = c5 + c6, s67 = c6 + c7, s74 = c7 + c4;
+    // zeta-edges 13..16
+    const T e4 = t4 - s04, e5 = t5 - s15, e6 = t6 - s26, e7 = t7 - s37;
 
-    // xi-edge midpoints 9, 11, 17, 19
-    const W3<T> B0 = add_t(b00, b10), B1 = add_t(b01, b11);
-    const W3<T> C0 = add_t(c00, c10), C1 = add_t(c01, c11);
-    const T d0 = triple_t(a00, B0, C0), d2 = triple_t(a10, B0, C1);
-    const T d8 = triple_t(a01, B1, C0), d10 = triple_t(a11, B1, C1);
-    T md = check_edges ? fmin(fmin(d0, d2), fmin(d8, d10)) : T(0);
-    T me = fmin(fmin(d0 - s01, d2 - s23), fmin(d8 - s45, d10 - s67));
-    const T h02 = d0 + d2, h810 = d8 + d10, p08 = d0 + d8, p210 = d2 + d10;
-    // eta-edge midpoints 10, 12, 18, 20
-    const W3<T> A0 = add_t(a00, a10), A1 = add_t(a01, a11);
-    const W3<T> Cq0 = add_t(c00, c01), Cq1 = add_t(c10, c11);
-    const T d1 = triple_t(A0, b10, Cq1), d3 = triple_t(A0, b00, Cq0);
-    const T d9 = triple_t(A1, b11, Cq1), d11 = triple_t(A1, b01, Cq0);
-    if (check_edges) md = fmin(md, fmin(fmin(d1, d3), fmin(d9, d11)));
-    me = fmin(me, fmin(fmin(d1 - s12, d3 - s30), fmin(d9 - s56, d11 - s74)));
-    const T dz0 = h02 + (d1 + d3), dz1 = h810 + (d9 + d11);
-    const T p19 = d1 + d9, p311 = d3 + d11;
-    // zeta-edge midpoints 13..16
-    const W3<T> Aq0 = add_t(a00, a01), Aq1 = add_t(a10, a11);
-    const W3<T> Bq0 = add_t(b00, b01), Bq1 = add_t(b10, b11);
-    const T d4 = triple_t(Aq0, Bq0, c00), d5 = triple_t(Aq0, Bq1, c10);
-    const T d6 = triple_t(Aq1, Bq1, c11), d7 = triple_t(Aq1, Bq0, c01);
-    if (check_edges) md = fmin(md, fmin(fmin(d4, d5), fmin(d6, d7)));
-    me = fmin(me, fmin(fmin(d4 - s04, d5 - s15), fmin(d6 - s26, d7 - s37)));
-    const T v45 = d4 + d5, v67 = d6 + d7;
-
+    // step 2 with the edge midpoints (4 J = 2 b_e + v_p + v_q)
+    T md = T(0);
+    if (check_edges) {
+        md = fmin(fmin(fmin(e0 + s01, e1 + s12), fmin(e2 + s23, e3 + s30)),
+                  fmin(fmin(e4 + s04, e5 + s15), fmin(e6 + s26, e7 + s37)));
+        md = fmin(md, fmin(fmin(e8 + s45, e9 + s56), fmin(e10 + s67, e11 + s74)));
+    }
+    const T me = fmin(fmin(fmin(fmin(e0, e1), fmin(e2, e3)), fmin(fmin(e4, e5), fmin(e6, e7))),
+                      fmin(fmin(e8, e9), fmin(e10, e11)));
+    // Table 3 in the form of element_values
+    const T ez0 = (e0 + e2) + (e1 + e3), ez1 = (e8 + e10) + (e9 + e11);
     const T cz0 = s01 + s23, cz1 = s45 + s67;
-    T mf = fmin(fma(T(-3), cz0, dz0), fma(T(-3), cz1, dz1));
-    mf = fmin(mf, fmin(fma(T(-3), s01 + s45, p08 + v45), fma(T(-3), s12 + s56, p19 + (d5 + d6))));
-    mf = fmin(mf, fmin(fma(T(-3), s23 + s67, p210 + v67), fma(T(-3), s30 + s74, p311 + (d4 + d7))));
-    const T z = fma(T(-5), cz0 + cz1, (dz0 + dz1) + (v45 + v67));
+    const T e45 = e4 + e5, e67 = e6 + e7;
+    T mf = fmin(ez0 - cz0, ez1 - cz1);
+    mf = fmin(mf, fmin(((e0 + e8) + e45) - (s01 + s45), ((e1 + e9) + (e5 + e6)) - (s12 + s56)));
+    mf = fmin(mf, fmin(((e2 + e10) + e67) - (s23 + s67), ((e3 + e11) + (e4 + e7)) - (s30 + s74)));
+    const T z = fma(T(-2), cz0 + cz1, (ez0 + ez1) + (e45 + e67));
 
     const T m8 = fmin(fmin(fmin(c0, c1), fmin(c2, c3)), fmin(fmin(c4, c5), fmin(c6, c7)));
     LeanT<T> r;
@@ -418,12 +486,14 @@ HEXVAL_HD LeanResult element_lean(const V3 p[8], bool check_edges)
 }
 
 // FP32 filter thresholds, in units of u32 M^ (u32 = 2^-24).  Each edge
-// component carries one FP64 and one FP32 rounding (relative u32 (1 + 2^-29));
-// everything after follows the FP64 derivation with u -> u32, whose
-// multipliers (8.01, 40.01, 32.01, 85.01, 150.02) keep their slack at this
-// precision (second-order terms are below 1e-5 of the first).  The FP32
-// values of the guard keep all products in the normal range with a margin
-// far above the underflow error.
+// component carries one FP64 and one FP32 rounding (relative u32 (1 + 2^-29)),
+// which adds 4u to a corner cross component (7u instead of 3u) and doubles the
+// error of a pair sum (4u); the FP64 derivation with u -> u32 then gives
+// corner values 6.5, xi/eta 2 b_e 16, zeta 2 b_e 55, edge-midpoint values
+// 11, b_f 59 and b_27 90.5 (u32 M), inside kTauValue and kTauCoeff with the
+// same margin as in FP64 (second-order terms are below 1e-5 of the first).
+// The FP32 values of the guard keep all products in the normal range with a
+// margin far above the underflow error.
 constexpr float kU32 = 5.9604644775390625e-08f;   // 2^-24
 
 // Outcome of the FP32 pass: 0 INVALID, 1 VALID (both certain), -1 recheck in FP64.

@@ -315,6 +315,8 @@ int check_opts(const hexval_opts_t* o)
         return fail(HEXVAL_E_ARG, "block_threads must be 0 or a multiple of 64 in 64..256");
     if (o->queue_capacity < 0) return fail(HEXVAL_E_ARG, "queue_capacity must be >= 0");
     if (o->grid_blocks < 0 || o->grid_blocks > (1ll << 30)) return fail(HEXVAL_E_ARG, "grid_blocks out of range");
+    if (o->walk_layers < -1 || o->walk_layers > 64) return fail(HEXVAL_E_ARG, "walk_layers must be in -1..64");
+    if (o->reserved != 0) return fail(HEXVAL_E_ARG, "reserved must be 0");
     return HEXVAL_OK;
 }
 
@@ -385,16 +387,19 @@ static int exact_tier(Workspace& w, const double* pts, uint8_t* v, uint8_t* hv, 
 
 // ---------------------------------------------------------------- autotuner
 // Launch shape of the first-pass kernel: threads per block (= elements per
-// tile) and a persistent grid of k blocks per CU (4, 8, 16 or 32) taking
-// tiles at run time.  Picked by timing every candidate twice on the call's
-// own input (the better time counts), cached per (device architecture,
-// precision, gather mode, batched, log2 size bucket) and optionally
-// persisted in the file named by HEXVAL_TUNE_CACHE.  The per-element
-// arithmetic never depends on the launch shape.
+// tile), a persistent grid of k blocks per CU (4, 8, 16 or 32) taking tiles
+// at run time and, for a single mesh with trusted connectivity in FP64, the
+// column walk's layers per tile (0: plain tiles, or kWalkLayers).  Picked by
+// timing every candidate twice on the call's own input (the better time
+// counts), cached per (device architecture, precision, gather mode, batched,
+// log2 size bucket) and optionally persisted in the file named by
+// HEXVAL_TUNE_CACHE.  The per-element arithmetic never depends on the launch
+// shape.
 
 struct TuneChoice {
     int block = 256;
     int per_cu = 4;    // persistent grid of per_cu blocks per CU (tiles are handed out at run time)
+    int walk = kWalkLayers;   // layers per column tile of the walking pass, 0 = plain tiles
 };
 
 static std::mutex g_tune_mu;
@@ -406,7 +411,7 @@ static std::string tune_key(const char* arch, int precision, int gather, bool ba
     int bucket = 0;
     while ((1ll << (bucket + 1)) <= total) ++bucket;
     char buf[128];
-    snprintf(buf, sizeof buf, "v2/%s/p%d/g%d/b%d/n%d", arch, precision, gather, batched ? 1 : 0, bucket);
+    snprintf(buf, sizeof buf, "v3/%s/p%d/g%d/b%d/n%d", arch, precision, gather, batched ? 1 : 0, bucket);
     return buf;
 }
 
@@ -419,11 +424,12 @@ static void tune_load_locked()
     FILE* f = fopen(path, "r");
     if (!f) return;
     char key[128];
-    int block, per_cu;
-    while (fscanf(f, "%127s %d %d", key, &block, &per_cu) == 3) {
+    int block, per_cu, walk;
+    while (fscanf(f, "%127s %d %d %d", key, &block, &per_cu, &walk) == 4) {
         TuneChoice c;
         c.block = block;
         c.per_cu = per_cu;
+        c.walk = walk;
         g_tune[key] = c;
     }
     fclose(f);
@@ -436,7 +442,7 @@ static void tune_store_locked(const std::string& key, const TuneChoice& c)
     if (!path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d\n", key.c_str(), c.block, c.per_cu);
+    fprintf(f, "%s %d %d %d\n", key.c_str(), c.block, c.per_cu, c.walk);
     fclose(f);
 }
 
@@ -579,6 +585,13 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     };
     const bool timing = st && st->timing && w.ev[0];   // workspaces without events do not time
     const int xcds = 8;
+    // A single mesh with trusted connectivity may walk columns of stacked
+    // elements (k_top_f64_walk, k_filter_f32_walk): the tuned choice, unless
+    // the options fix it
+    const bool walk_able = !batched && gather == 2;
+    if (o.walk_layers) choice.walk = o.walk_layers > 0 ? o.walk_layers : 0;
+    int walk_now = walk_able ? choice.walk : 0;   // layers of the pass being launched
+    bool walk = walk_now > 0;
     auto first_args = [&]() {
         TopArgs ta{};
         ta.mesh = single;
@@ -590,7 +603,15 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         ta.max_depth = o.max_depth;
         ta.xcds = xcds;
         ta.batch_conn = batch_conn ? 1 : 0;
+        ta.walk_layers = walk ? walk_now : 0;
+        ta.walk_limit = walk ? std::min<int64_t>(total, kWalkSearch) : 0;
         return ta;
+    };
+    // the column walk needs the stack stride of this mesh, found after each
+    // counter reset (the walking pass reads it on the device)
+    auto reset = [&]() {
+        launch_reset(w.cnt, s);
+        if (walk) launch_walk_detect(single.conn, total, std::min<int64_t>(total, kWalkSearch), w.cnt, s);
     };
     auto launch_first = [&](const TopArgs& ta, int64_t g, int blk) {
         if (o.precision == HEXVAL_FP32_FILTER) launch_filter_range(ta, batched, (int)g, blk, s);
@@ -599,17 +620,22 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     if (need_tune) {
         static const int kBlocks[3] = {64, 128, 256};
         static const int kPerCu[4] = {4, 8, 16, 32};
+        const int n_walk = walk_able && !o.walk_layers ? 2 : 1;
+        const TuneChoice fixed_walk = choice;
         float best = 1e30f;
         for (int blk : kBlocks) {
             if ((rc = setup_tiles(blk))) return rc;
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < 4 * n_walk; ++k) {
                 TuneChoice c;
                 c.block = blk;
-                c.per_cu = kPerCu[k];
+                c.per_cu = kPerCu[k % 4];
+                c.walk = n_walk == 2 ? (k < 4 ? 0 : kWalkLayers) : fixed_walk.walk;
+                walk_now = walk_able ? c.walk : 0;
+                walk = walk_now > 0;
                 const int64_t g = grid_for(c, n_tiles, cus);
                 float ms = 0.0f;
                 for (int rep = 0; rep < 2; ++rep) {
-                    launch_reset(w.cnt, s);
+                    reset();
                     HX_HIP(hipEventRecord(w.ev[0], s));
                     launch_first(first_args(), g, blk);
                     HX_HIP(hipEventRecord(w.ev[1], s));
@@ -623,8 +649,12 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
                 }
             }
         }
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_store_locked(key, choice);
+        walk_now = walk_able ? choice.walk : 0;
+        walk = walk_now > 0;
+        if (!o.walk_layers) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            tune_store_locked(key, choice);
+        }
     }
     if ((rc = setup_tiles(choice.block))) return rc;
     const int block = choice.block;
@@ -633,6 +663,7 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     if (st) {
         st->block_threads = block;
         st->grid_blocks = grid;
+        st->walk_layers = walk_now;
     }
     const int list_grid = cus * 8;
     // 4 blocks per CU: empty levels cost less to launch than at 8, and large
@@ -641,7 +672,8 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
 
     uint64_t prev_remaining = 0;
     for (int round = 0;; ++round) {
-        launch_reset(w.cnt, s);
+        if (round == 0) reset();
+        else launch_reset(w.cnt, s);
         const TopArgs ta = first_args();
         if (timing && round == 0) HX_HIP(hipEventRecord(w.ev[0], s));
         const bool filter = round == 0 && o.precision == HEXVAL_FP32_FILTER;
@@ -697,7 +729,13 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
             st->n_rounds = round + 1;
             if (round == 0) {
                 st->n_elements = total;
-                if (o.precision == HEXVAL_FP32_FILTER) st->n_recheck = (int64_t)std::min<uint64_t>(c.n_list, q.list_cap);
+                if (walk && c.walk_code) {
+                    // the stride the walking pass used (it walks none below kWalkMinStride)
+                    const int64_t stride = std::min<int64_t>(total, kWalkSearch) - (int64_t)c.walk_code;
+                    st->walk_stride = stride >= kWalkMinStride && stride < total ? stride : 0;
+                }
+                if (o.precision == HEXVAL_FP32_FILTER)
+                    st->n_recheck = (int64_t)std::min<uint64_t>(c.n_list, q.list_cap) + (int64_t)c.n_rechecked;
                 if (timing && o.precision == HEXVAL_FP32_FILTER) {
                     hipEventElapsedTime(&st->ms_first_pass, w.ev[0], w.ev[3]);
                     hipEventElapsedTime(&st->ms_recheck, w.ev[3], w.ev[1]);
@@ -806,6 +844,10 @@ int run_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts_in, do
     a.max_depth = o.max_depth;
     a.xcds = 8;
     const bool timing = st && st->timing;
+    // the first round over a trusted mesh walks columns of stacked elements
+    // (k_minj_top_walk) unless the options ask for plain tiles
+    const bool walk = mesh->connectivity && !o.validate_indices && o.walk_layers >= 0;
+    const int64_t walk_limit = std::min<int64_t>(n, kWalkSearch);
 
     // Rounds: a round subdivides at most root_cap elements (a quarter of the
     // store, the rest being room for their boxes); elements past it, or that
@@ -827,7 +869,10 @@ int run_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts_in, do
         a.final_round = final_round ? 1 : 0;
         a.root_cap = root_cap;
         a.n_tiles = (count + 255) / 256;
+        a.walk_layers = round == 0 && walk ? (o.walk_layers > 0 ? o.walk_layers : kWalkLayers) : 0;
+        a.walk_limit = walk_limit;
         launch_reset(w.cnt, s);
+        if (a.walk_layers) launch_walk_detect(mesh->connectivity, n, walk_limit, w.cnt, s);
         if (timing && round == 0) HX_HIP(hipEventRecord(w.ev[0], s));
         launch_minj_top(a, cus * 4, s);   // 4 blocks per CU: 2-3% faster than 8 on the 400^3 lattice
         if (timing && round == 0) HX_HIP(hipEventRecord(w.ev[1], s));

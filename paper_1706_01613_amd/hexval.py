@@ -38,7 +38,8 @@ class hexval_stats_t(ctypes.Structure):
                 ("ms_first_pass", ctypes.c_float), ("ms_recheck", ctypes.c_float),
                 ("ms_subdivision", ctypes.c_float), ("ms_total", ctypes.c_float),
                 ("block_threads", ctypes.c_int32), ("n_exact_host", ctypes.c_int32),
-                ("grid_blocks", ctypes.c_int64)]
+                ("grid_blocks", ctypes.c_int64), ("walk_layers", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("walk_stride", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -48,7 +49,8 @@ class hexval_opts_t(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_depth", ctypes.c_int32),
                 ("validate_indices", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("queue_capacity", ctypes.c_int64), ("grid_blocks", ctypes.c_int64),
-                ("stream", ctypes.c_void_p), ("stats", ctypes.POINTER(hexval_stats_t))]
+                ("stream", ctypes.c_void_p), ("stats", ctypes.POINTER(hexval_stats_t)),
+                ("walk_layers", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class hexval_request_t(ctypes.Structure):
@@ -134,7 +136,7 @@ def hexval_opts_default():
 
 
 def make_opts(precision=FP64, max_depth=6, validate_indices=False, block_threads=0,
-              queue_capacity=0, grid_blocks=0, stream=None, stats=None):
+              queue_capacity=0, grid_blocks=0, stream=None, stats=None, walk_layers=0):
     o = hexval_opts_default()
     o.precision = precision
     o.max_depth = max_depth
@@ -142,6 +144,7 @@ def make_opts(precision=FP64, max_depth=6, validate_indices=False, block_threads
     o.block_threads = block_threads
     o.queue_capacity = queue_capacity
     o.grid_blocks = grid_blocks
+    o.walk_layers = walk_layers
     o.stream = _stream_handle(stream)
     if stats is not None:
         o.stats = ctypes.pointer(stats)
@@ -259,7 +262,7 @@ def hexval_last_error():
 
 def check(points, connectivity=None, precision=FP64, max_depth=6, validate_indices=False,
           stream=None, stats=False, block_threads=0, grid_blocks=0, queue_capacity=0,
-          want_min=True):
+          want_min=True, walk_layers=0):
     """Allocate outputs (torch, on points' device) and run hexval_check_ex.
 
     points: [n,8,3] float64 (connectivity None) or [m,3] float64 with
@@ -274,7 +277,7 @@ def check(points, connectivity=None, precision=FP64, max_depth=6, validate_indic
     if stream is None:
         stream = torch.cuda.current_stream(points.device)
     opts = make_opts(precision, max_depth, validate_indices, block_threads, queue_capacity,
-                     grid_blocks, stream, st)
+                     grid_blocks, stream, st, walk_layers)
     hexval_check_ex(make_mesh(points, connectivity, n), opts, verdicts, mins)
     return verdicts, mins, (st.as_dict() if stats else None)
 

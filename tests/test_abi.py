@@ -26,17 +26,36 @@ def test_library_exports_every_declared_function():
         assert hasattr(L, name), name
 
 
+def test_calibration_library_exports_its_header():
+    header = os.path.join(ROOT, "include", "hexval_calib.h")
+    text = re.sub(r"/\*.*?\*/", "", open(header).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(hexval_calib_[a-z0-9_]+)\s*\(", text)))
+    assert names == ["hexval_calib_copy", "hexval_calib_fp64", "hexval_calib_read"]
+    L = ctypes.CDLL(os.path.join(ROOT, "paper_1706_01613_amd", "libhexval_calib.so"))
+    for name in names:
+        assert hasattr(L, name), name
+    # argument errors come back as status 1 without touching a GPU
+    f = ctypes.c_float()
+    d = ctypes.c_double()
+    L.hexval_calib_read.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]
+    assert L.hexval_calib_read(None, 1 << 20, 1, ctypes.byref(f)) == 1
+    L.hexval_calib_fp64.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p]
+    assert L.hexval_calib_fp64(0, 1, ctypes.byref(f), ctypes.byref(d), ctypes.byref(d)) == 1
+
+
 def test_struct_layouts_match_header_sizes():
-    # int64 alignment: mesh 32 B, opts 48 B, stats 88 B, request 64 B
+    # int64 alignment: mesh 32 B, opts 56 B, stats 104 B, request 64 B
     assert ctypes.sizeof(hx.hexval_mesh_t) == 32
-    assert ctypes.sizeof(hx.hexval_opts_t) == 48
-    assert ctypes.sizeof(hx.hexval_stats_t) == 88
+    assert ctypes.sizeof(hx.hexval_opts_t) == 56
+    assert ctypes.sizeof(hx.hexval_stats_t) == 104
     assert ctypes.sizeof(hx.hexval_request_t) == 64
 
 
 def test_defaults():
     o = hx.hexval_opts_default()
     assert (o.precision, o.max_depth, o.validate_indices, o.queue_capacity) == (hx.FP64, 6, 0, 0)
+    assert (o.walk_layers, o.reserved) == (0, 0)
 
 
 def _status(f, *args):
@@ -56,7 +75,8 @@ def test_argument_errors_without_gpu():
     assert L.hexval_check_ex(None, None, None, None) == hx.E_ARG
     mesh = hx.hexval_mesh_t(16, 0, None, 4)
     for field, value in [("max_depth", 21), ("max_depth", -1), ("precision", 7),
-                         ("block_threads", 100), ("block_threads", 512), ("queue_capacity", -5)]:
+                         ("block_threads", 100), ("block_threads", 512), ("queue_capacity", -5),
+                         ("walk_layers", -2), ("walk_layers", 65), ("reserved", 1)]:
         o = hx.hexval_opts_default()
         setattr(o, field, value)
         assert L.hexval_check_ex(ctypes.byref(mesh), ctypes.byref(o), 32, None) == hx.E_ARG, field

@@ -18,9 +18,10 @@ STRUCTS = {
     "hexval_mesh_t": ["points", "n_points", "connectivity", "n"],
     "hexval_stats_t": ["n_elements", "n_subdivided", "n_nodes", "n_exact", "n_recheck", "n_rounds",
                        "max_level", "timing", "ms_first_pass", "ms_recheck", "ms_subdivision",
-                       "ms_total", "block_threads", "n_exact_host", "grid_blocks"],
+                       "ms_total", "block_threads", "n_exact_host", "grid_blocks", "walk_layers",
+                       "reserved", "walk_stride"],
     "hexval_opts_t": ["precision", "max_depth", "validate_indices", "block_threads",
-                      "queue_capacity", "grid_blocks", "stream", "stats"],
+                      "queue_capacity", "grid_blocks", "stream", "stats", "walk_layers", "reserved"],
     "hexval_request_t": ["mesh", "host_points", "host_conn", "verdicts", "min_coeffs"],
 }
 

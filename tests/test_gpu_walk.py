@@ -1,0 +1,135 @@
+"""The column walk of the first passes (elements stacked with a stride found
+from the connectivity; each lane carries the shared face to the element
+above) on connectivity layouts that match the walk, break it in places or do
+not match it at all: every result equal to the oracle, and to the plain-tile
+pass bit for bit (HIP path through the C ABI)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1706_01613_amd import hexval as hx
+from paper_1706_01613_amd import synth
+from tests._gpu import assert_parity, say, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+NX, NY, NZ = 70, 65, 50          # 4550 elements per layer: above the smallest stride walked
+
+
+def lattice(jitter=0.05, seed=11):
+    return synth.warped_lattice(NX, NY, NZ, seed=seed, jitter_fraction=jitter)
+
+
+def run(torch, V, C, walk, precision=hx.FP64, max_depth=6):
+    v, m, st = hx.check(to_dev(torch, V), to_dev(torch, C), precision=precision, max_depth=max_depth,
+                        stats=True, walk_layers=walk)
+    torch.cuda.synchronize()
+    return v.cpu().numpy(), m.cpu().numpy(), st
+
+
+def check_layout(torch, V, C, label, expect_stride=None, precisions=(hx.FP64, hx.FP32_FILTER)):
+    for prec in precisions:
+        base_v, base_m, st0 = run(torch, V, C, -1, prec)
+        assert st0["walk_layers"] == 0
+        assert_parity(base_v, base_m if prec == hx.FP64 else None, V, C, label=f"{label} plain")
+        for walk in (16, 3, 64):
+            v, m, st = run(torch, V, C, walk, prec)
+            say(f"{label} precision {prec} walk {walk}: stride {st['walk_stride']}, rounds {st['n_rounds']}")
+            assert st["walk_layers"] == walk
+            assert st["n_recheck"] == st0["n_recheck"], "FP32 filter decisions differ"
+            if expect_stride is not None:
+                assert st["walk_stride"] == expect_stride
+            assert np.array_equal(v, base_v), f"{label}: walk {walk} verdicts differ from plain tiles"
+            assert np.array_equal(m.view(np.int64), base_m.view(np.int64)), f"{label}: walk {walk} min_coeff"
+
+
+def test_lattice_walks_with_its_layer_stride():
+    torch = torch_cuda()
+    V, C = lattice()
+    check_layout(torch, V, C, "lattice", expect_stride=NX * NY)
+
+
+def test_partial_last_layer_and_single_layer_tiles():
+    torch = torch_cuda()
+    V, C = lattice()
+    n = C.shape[0] - 1234
+    check_layout(torch, V, C[:n], "partial layer", expect_stride=NX * NY)
+
+
+def test_permuted_elements_take_the_full_gather():
+    torch = torch_cuda()
+    V, C = lattice()
+    perm = np.random.default_rng(3).permutation(C.shape[0])
+    check_layout(torch, V, C[perm], "permuted")
+
+
+def test_broken_structure_falls_back_per_lane():
+    torch = torch_cuda()
+    V, C = lattice(jitter=0.2)
+    rng = np.random.default_rng(4)
+    C = C.copy()
+    rows = rng.choice(C.shape[0], C.shape[0] // 10, replace=False)
+    C[rows] = C[rng.integers(0, C.shape[0], rows.size)]          # other elements' rows
+    flip = rng.choice(C.shape[0], 500, replace=False)
+    C[flip] = C[flip][:, [4, 5, 6, 7, 0, 1, 2, 3]]                # reflected: invalid
+    check_layout(torch, V, C, "broken", expect_stride=NX * NY)
+
+
+def test_two_lattices_with_different_layers():
+    torch = torch_cuda()
+    V1, C1 = lattice(seed=5)
+    V2, C2 = synth.warped_lattice(90, 80, 7, seed=6, jitter_fraction=0.3)
+    V = np.concatenate([V1, V2])
+    C = np.concatenate([C1, C2 + V1.shape[0]]).astype(np.int32)
+    check_layout(torch, V, C, "two lattices", expect_stride=NX * NY)
+
+
+def test_stacked_part_then_independent_near_degenerate_hexes():
+    # as the precision-stress mesh: the walk covers the lattice's layers and
+    # the appended hexes (every one uncertain in FP32) come as plain tiles
+    torch = torch_cuda()
+    V, C = lattice()
+    V, C = synth.append_independent(V, C, synth.near_degenerate_hexes(9000, seed=8))
+    check_layout(torch, V, C, "lattice + near-degenerate", expect_stride=NX * NY)
+
+
+def test_small_layers_are_not_walked():
+    torch = torch_cuda()
+    V, C = synth.warped_lattice(30, 30, 40, seed=7, jitter_fraction=0.1)   # 900 per layer
+    check_layout(torch, V, C, "small layers", expect_stride=0)
+
+
+def test_tiny_and_single_element_meshes():
+    torch = torch_cuda()
+    V, C = lattice()
+    for n in (1, 7, 255, 4551):
+        check_layout(torch, V, C[:n], f"first {n}", precisions=(hx.FP64,))
+
+
+def test_walk_at_depth_cap_zero_and_edges():
+    torch = torch_cuda()
+    V, C = lattice(jitter=0.4)
+    for walk in (-1, 16):
+        v, m, _ = run(torch, V, C, walk, max_depth=0)
+        assert_parity(v, m, V, C, max_depth=0, label=f"cap 0 walk {walk}")
+
+
+def test_min_jacobian_walk_equals_plain_tiles():
+    torch = torch_cuda()
+    V, C = lattice(jitter=0.3)
+    pts, conn = to_dev(torch, V), to_dev(torch, C)
+    res = {}
+    for walk in (-1, 16):
+        n = C.shape[0]
+        lo = torch.empty(n, dtype=torch.float64, device="cuda")
+        hi = torch.empty_like(lo)
+        status = torch.empty(n, dtype=torch.uint8, device="cuda")
+        opts = hx.make_opts(walk_layers=walk, stream=torch.cuda.current_stream())
+        hx.hexval_min_jacobian(hx.make_mesh(pts, conn, n), opts, 1e-3, lo, hi, status)
+        torch.cuda.synchronize()
+        res[walk] = (lo.cpu().numpy(), hi.cpu().numpy(), status.cpu().numpy())
+    for a, b in zip(res[-1], res[16]):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    ref = oracle.min_jacobian(V, C, rtol=1e-3, max_depth=6)
+    lo, hi, _ = res[16]
+    assert not np.any((lo > ref["hi"]) | (ref["lo"] > hi)), "disjoint min J intervals"
