@@ -39,12 +39,14 @@ def algorithmic_bytes(n_hex, n_vert, with_min=True):
 # add, multiply, FMA or min per lane per clock).
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # FP64 arithmetic operations per hex of the first pass (add, sub, mul, FMA,
-# min each counted once): 36 edge differences, 36 pair sums, 20 triple
-# products at 9 operations, about 80 for Table 3 and about 40 for the minima
-# and the decisions.
-VALU_OPS_PER_HEX = 36 + 36 + 20 * 9 + 80 + 40
+# min, max each counted once): 36 edge differences, 35 for the scale bound,
+# 8 corner cross products (6 each) and their dot products (3 each), 8 xi/eta
+# 2 b_e as six-product dot chains (6 each), 56 for the zeta-edges (pair sums,
+# 4 triple products, corner sums, subtractions), 38 for the face and centre
+# sums of Table 3, 29 for the minima and the final scalings.
+VALU_OPS_PER_HEX = 36 + 35 + 8 * 6 + 8 * 3 + 8 * 6 + 56 + 38 + 29
 KERNEL_SOURCES = ["hexval_kernels.hip", "hexval_kernels.hpp", "hexval_math.hpp", "hexval_internal.hpp"]
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_top_f64_conn_lattice400_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "first_pass_fp64_lattice400_traffic.md")
 
 
 def kernel_source_digest():
@@ -386,7 +388,8 @@ def min_jacobian_leg(hx, torch, V, C, pts, conn, steps, stream, work, rtol=1e-3)
     gbps = alg / (st.ms_first_pass * 1e-3) / 1e9
     return {"workload": "min J to rtol 1e-3 (certified bounds), same 400^3 lattice, cap 6",
             "value": n / wall, "unit": "hex/s", "ms_per_step": 1e3 * wall, "status_counts": hist,
-            "first_pass": {"kernel": "k_minj_top_conn", "ms": st.ms_first_pass,
+            "first_pass": {"kernel": "k_minj_top_walk" if st.walk_layers else "k_minj_top_conn",
+                           "ms": st.ms_first_pass,
                            "algorithmic_bytes": alg, "achieved_GBps": gbps, "frac_of_8TBps": gbps / 8000.0},
             "stats": st.as_dict()}
 
@@ -571,7 +574,8 @@ def main():
                    "inputs": "resident in HBM"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_top_f64_conn (first pass)",
+                     "kernel": ("k_top_f64_walk" if stats[-1]["walk_layers"] else "k_top_f64_conn")
+                               + " (first pass)",
                      "algorithmic_bytes_per_launch": alg,
                      "avg_launch_ms": float(first.mean()),
                      "valu": {"achieved": valu_ops, "peak": VALU_PEAK_OPS, "unit": "FP64 lane-ops/s",

@@ -1234,6 +1234,120 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a)
     }
 }
 
+// ------------------------------------------------ depth-first subdivision
+//
+// The level-by-level subdivision keeps a whole level of every listed
+// element's tree in the store.  An element whose ambiguous region is a
+// surface (min J = 0 along a curve, say) needs about 4^L sub-boxes at level L,
+// more than any store holds at deep caps.  Such elements, when a round with a
+// single listed element still overflows, are decided here instead, as the
+// recursion of Section 6 does: depth first, one lane per element, keeping
+// only the path from the root (one node per level) and the next child to
+// visit at each level.  The decisions are those of the level kernel
+// (level_decide), and the verdict folds the same flags (INVALID > exact >
+// UNDECIDED > VALID), so it is the level-by-level verdict.
+
+// Child cursor of a stack node (word 28).
+__device__ __forceinline__ int dfs_cursor(const double* nd) { return (int)__double_as_longlong(nd[28]); }
+__device__ __forceinline__ void dfs_set_cursor(double* nd, int c) { nd[28] = __longlong_as_double((long long)c); }
+
+// Depth-first walk of the tree below the root in st[0..26] (tensor order);
+// st holds max_depth + 1 nodes of 32 words.  Returns the element's flags.
+__device__ uint32_t dfs_subdivide(double* st, double scale, int max_depth)
+{
+    uint32_t flags = 0;
+    dfs_set_cursor(st, 0);
+    int L = 0;
+    while (L >= 0) {
+        double* nd = st + 32 * L;
+        const int c = dfs_cursor(nd);
+        if (c == 8) {
+            --L;
+            continue;
+        }
+        dfs_set_cursor(nd, c + 1);
+        double t[27];
+#pragma unroll
+        for (int k = 0; k < 27; ++k) t[k] = nd[mirrored(k, c)];
+        lower_octant(t);
+        const int d = level_decide(t, scale, L + 1, max_depth);
+        if (d == kChildInvalid) return flags | kFlagInvalid;
+        if (d == kChildInexact) {
+            flags |= kFlagExact;
+        } else if (d == kChildUndecided) {
+            flags |= kFlagUndecided;
+        } else if (d == kChildPush) {
+            double* ch = nd + 32;
+#pragma unroll
+            for (int k = 0; k < 27; ++k) ch[mirrored(k, c)] = t[k];   // the child in its own orientation
+            dfs_set_cursor(ch, 0);
+            ++L;
+        }
+    }
+    return flags;
+}
+
+__global__ __launch_bounds__(64) void k_dfs(DfsArgs a)
+{
+    const QueueDev& q = a.q;
+    const unsigned long long cnt = *(&q.cnt->n_list);
+    const int64_t n = (int64_t)(cnt < q.list_cap ? cnt : q.list_cap);
+    const int64_t lane = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double* st = reinterpret_cast<double*>(q.nodes) + 32 * (a.max_depth + 1) * lane;
+    // lane l (below a.lanes, the stacks the store holds) takes the elements
+    // l, l + lanes, ...; whole waves iterate together (wave-level list
+    // appends) until none of their lanes has an element left
+    for (int64_t i = lane;; i += a.lanes) {
+        const bool active = lane < a.lanes && i < n;
+        if (!ballot(active)) break;
+        int64_t e = 0;
+        int mi = 0;
+        uint8_t v = 0;
+        bool exact = false;
+        if (active) {
+            e = q.list_elem[i];
+            mi = q.list_mesh[i];
+            const MeshDev m = a.meshes ? a.meshes[mi] : a.mesh;
+            V3 p[8];
+            bool bad = false;
+            load_points(m, e, p, bad);
+            if (bad) {
+                v = 3;
+            } else {
+                ElementValues r;
+                element_values(p, r);
+                const int ts = top_state(r, summarize(r), a.max_depth);
+                if (ts == kTopSubdivide) {
+#pragma unroll
+                    for (int k = 0; k < 27; ++k) st[fig3_to_tensor(k)] = coefficient(r, k);
+                    const uint32_t f = dfs_subdivide(st, r.scale, a.max_depth);
+                    v = (f & kFlagInvalid) ? 0 : (f & kFlagExact) ? kExact : (f & kFlagUndecided) ? 2 : 1;
+                } else {
+                    v = ts == kTopExact ? kExact : (uint8_t)ts;
+                }
+                exact = v == kExact;
+            }
+        }
+        bool deferred = false;
+        const uint64_t xmask = ballot(exact);
+        if (xmask) {
+            const unsigned long long x = wave_reserve(&q.cnt->n_exact, xmask);
+            if (exact && x < q.exact_cap) {
+                q.exact_elem[x] = e;
+                q.exact_mesh[x] = mi;
+            } else if (exact) {
+                v = kDeferred;
+                deferred = true;
+            }
+        }
+        wave_count(&q.cnt->n_deferred, deferred);
+        if (active) {
+            const MeshDev m = a.meshes ? a.meshes[mi] : a.mesh;
+            m.verdict[e] = v;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_fold(FoldArgs a)
 {
     const QueueDev& q = a.q;
@@ -1922,6 +2036,19 @@ __global__ __launch_bounds__(64) void k_exact_device(const double* pts, uint8_t*
         out[i] = mode == 2 ? exact_device_quad(pts + 8 * i) : exact_device_hex(pts + 24 * i, max_depth, mode == 1);
 }
 
+// Exact subdivision of the elements the device tier marked kExactSubdivide:
+// lane l takes the elements l, l + lanes, ... with its path in `stack`
+// ((max_depth + 1) * kExactDfsWords words per lane).
+__global__ __launch_bounds__(64) void k_exact_dfs(const double* pts, uint8_t* out, int64_t n, int max_depth,
+                                                  IW* stack, int64_t lanes)
+{
+    const int64_t lane = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (lane >= lanes) return;
+    IW* st = stack + lane * (int64_t)(max_depth + 1) * kExactDfsWords;
+    for (int64_t i = lane; i < n; i += lanes)
+        if (out[i] == kExactSubdivide) out[i] = exact_device_verdict(pts + 24 * i, max_depth, st);
+}
+
 // ------------------------------------------------------------ small kernels
 
 __global__ void k_reset(Counters* c)
@@ -2077,6 +2204,18 @@ void launch_tile_table(const MeshDev* meshes, int n_meshes, int tile, int32_t* t
 void launch_collect_deferred(const CollectArgs& a, int grid, hipStream_t s)
 {
     HX_LAUNCH(k_collect_deferred, grid, 256, s, a);
+}
+void launch_exact_dfs(const double* pts, uint8_t* out, int64_t n, int max_depth, void* stack, int64_t lanes,
+                      hipStream_t s)
+{
+    const int64_t g = (lanes + 63) / 64;
+    HX_LAUNCH(k_exact_dfs, g < 1024 ? g : 1024, 64, s, pts, out, n, max_depth, (IW*)stack,
+              lanes < 1024 * 64 ? lanes : 1024 * 64);
+}
+void launch_dfs(const DfsArgs& a, hipStream_t s)
+{
+    const int64_t g = (a.lanes + 63) / 64;
+    HX_LAUNCH(k_dfs, g < 4096 ? g : 4096, 64, s, a);
 }
 void launch_gather_exact(const GatherArgs& a, hipStream_t s)
 {

@@ -39,6 +39,18 @@ struct FoldArgs {
     const MeshDev* meshes;
 };
 
+// Depth-first subdivision of listed elements in bounded memory: lane i keeps
+// its path of sub-boxes in nodes [i (max_depth+1), (i+1) (max_depth+1)) of
+// the store.
+struct DfsArgs {
+    QueueDev q;
+    MeshDev mesh;
+    const MeshDev* meshes;
+    int64_t lanes;        // stacks that fit in the store
+    int32_t max_depth;
+    int32_t pad;
+};
+
 struct CollectArgs {
     QueueDev q;
     MeshDev mesh;
@@ -132,11 +144,20 @@ void launch_fold(const FoldArgs& a, int grid, hipStream_t s);
 void launch_reset(Counters* c, hipStream_t s);
 void launch_tile_table(const MeshDev* meshes, int n_meshes, int tile, int32_t* tile_mesh, hipStream_t s);
 void launch_collect_deferred(const CollectArgs& a, int grid, hipStream_t s);
+// Decides the listed elements (Q.list_elem, n_list entries) with a
+// depth-first subdivision per lane: verdicts final, or kExact with the element
+// on the exact list, or kDeferred when that list is full.
+void launch_dfs(const DfsArgs& a, hipStream_t s);
 void launch_gather_exact(const GatherArgs& a, hipStream_t s);
 void launch_scatter_exact(const ScatterArgs& a, hipStream_t s);
 void launch_coefficients(const MeshDev& m, double* out, hipStream_t s);
 // Device exact tier over gathered points (mode 0 verdict, 1 corner-only test,
 // 2 quadrangle); out[i] = result, or 0xFE where the host tier must decide.
 void launch_exact_device(const double* pts, uint8_t* out, int64_t n, int mode, int max_depth, hipStream_t s);
+// Exact subdivision of the elements launch_exact_device marked 0xFC, with
+// `lanes` paths of (max_depth + 1) levels in `stack` (device memory of
+// lanes * (max_depth + 1) * 28 * 48 bytes); results replace the marks.
+void launch_exact_dfs(const double* pts, uint8_t* out, int64_t n, int max_depth, void* stack, int64_t lanes,
+                      hipStream_t s);
 
 }  // namespace hexval

@@ -18,6 +18,7 @@
 
 #include "hexval.h"
 #include "hexval_exact.hpp"
+#include "hexval_exact_dev.hpp"
 #include "hexval_internal.hpp"
 #include "hexval_kernels.hpp"
 #include "hexval_runtime.hpp"
@@ -346,19 +347,27 @@ static uint64_t pow2_ceil(uint64_t x)
 enum class ExactKind { kVerdict, kCornerTest, kQuad };
 
 // Device exact tier over the n gathered elements in `pts` (device), then the
-// host tier for those it leaves (0xFE); results in `v` (device) and `hv`
+// host tier for those it leaves (coordinate spans beyond its integers, or
+// exact subdivision when the store has no room for a path); results in `v`
+// (device) and `hv`
 // (host).  Returns the number settled on the host.
 static int exact_tier(Workspace& w, const double* pts, uint8_t* v, uint8_t* hv, double* hpts, int64_t n,
                       int per, ExactKind kind, int max_depth, hipStream_t s, int64_t* host_count)
 {
     launch_exact_device(pts, v, n, kind == ExactKind::kQuad ? 2 : kind == ExactKind::kCornerTest ? 1 : 0,
                         max_depth, s);
+    if (kind == ExactKind::kVerdict && max_depth > 0) {
+        // exact subdivision on the device, the paths in the (idle) subdivision store
+        const int64_t per_lane = (int64_t)(max_depth + 1) * kExactDfsWords * (int64_t)sizeof(IW);
+        const int64_t lanes = (int64_t)(w.node_cap * sizeof(Node)) / per_lane;
+        if (lanes > 0) launch_exact_dfs(pts, v, n, max_depth, w.nodes, lanes, s);
+    }
     HX_HIP(hipGetLastError());
     HX_HIP(hipMemcpyAsync(hv, v, n, hipMemcpyDeviceToHost, s));
     HX_HIP(hipStreamSynchronize(s));
     std::vector<int64_t> left;
     for (int64_t i = 0; i < n; ++i)
-        if (hv[i] == 0xFE) left.push_back(i);
+        if (hv[i] == kHostExact || hv[i] == kExactSubdivide) left.push_back(i);
     *host_count = (int64_t)left.size();
     if (left.empty()) return HEXVAL_OK;
     HX_HIP(hipMemcpyAsync(hpts, pts, n * per * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -381,7 +390,6 @@ static int exact_tier(Workspace& w, const double* pts, uint8_t* v, uint8_t* hv, 
     }
     for (auto& x : th) x.join();
     HX_HIP(hipMemcpyAsync(v, hv, n, hipMemcpyHostToDevice, s));
-    (void)w;
     return HEXVAL_OK;
 }
 
@@ -671,6 +679,11 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     const int level_grid = cus * 4;
 
     uint64_t prev_remaining = 0;
+    // Once a round listing a single element still overflows the store, the
+    // elements left are decided depth first, one lane each, with their path
+    // of sub-boxes in the store (k_dfs): bounded memory, the same verdicts.
+    bool dfs_round = false;
+    const int64_t dfs_lanes = (int64_t)(q.node_cap / (uint64_t)(o.max_depth + 1));
     for (int round = 0;; ++round) {
         if (round == 0) reset();
         else launch_reset(w.cnt, s);
@@ -686,7 +699,12 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         } else {
             CollectArgs ca{q, single, dmeshes, batched ? n_meshes : 1};
             launch_collect_deferred(ca, list_grid, s);
-            launch_top_list(ta, batched, list_grid, block, s);
+            if (dfs_round) {
+                DfsArgs da{q, single, dmeshes, dfs_lanes, o.max_depth, 0};
+                launch_dfs(da, s);
+            } else {
+                launch_top_list(ta, batched, list_grid, block, s);
+            }
         }
         if (timing && round == 0) HX_HIP(hipEventRecord(w.ev[1], s));
         HX_HIP(hipGetLastError());
@@ -695,8 +713,8 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         // (a host round trip costs more than the launches, and such meshes
         // usually list some element); small ones read the counters first and
         // skip it when nothing was listed.
-        bool subdivide = true;
-        if (total < kEagerSubdivision) {
+        bool subdivide = !dfs_round;
+        if (subdivide && total < kEagerSubdivision) {
             HX_HIP(hipMemcpyAsync(w.hcnt, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
             HX_HIP(hipStreamSynchronize(s));
             subdivide = w.hcnt->n_sub > 0;
@@ -710,6 +728,9 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
             }
             FoldArgs fa{q, single, dmeshes};
             launch_fold(fa, cus * 2, s);
+            HX_HIP(hipGetLastError());
+            HX_HIP(hipMemcpyAsync(w.hcnt, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        } else if (dfs_round) {
             HX_HIP(hipGetLastError());
             HX_HIP(hipMemcpyAsync(w.hcnt, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
         }
@@ -772,10 +793,12 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
             const uint64_t listed = std::min<uint64_t>(prev_remaining, q.list_cap);
             if (c.n_deferred >= listed) {
                 // nothing completed: the listed elements' trees crowded each
-                // other out; list fewer per round, down to one at a time
-                if (q.root_cap <= 1)
+                // other out; list fewer per round, down to one at a time,
+                // then go depth first
+                if (dfs_round || (q.root_cap <= 1 && dfs_lanes < 1))
                     return fail(HEXVAL_E_QUEUE, "subdivision queue of %llu nodes too small to make progress",
                                 (unsigned long long)q.node_cap);
+                if (q.root_cap <= 1) dfs_round = true;
                 q.root_cap = std::max<uint64_t>(1, q.root_cap / 8);
             }
             remaining = prev_remaining - listed + c.n_deferred;
@@ -920,6 +943,7 @@ int run_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts_in, do
         st->n_subdivided = (int64_t)tot_sub;
         st->n_nodes = (int64_t)tot_nodes;
         st->max_level = max_level;
+        st->walk_layers = walk ? (o.walk_layers > 0 ? o.walk_layers : kWalkLayers) : 0;
         if (timing) {
             hipEventElapsedTime(&st->ms_first_pass, w.ev[0], w.ev[1]);
             hipEventElapsedTime(&st->ms_subdivision, w.ev[1], w.ev[2]);

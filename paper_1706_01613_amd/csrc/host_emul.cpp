@@ -175,6 +175,10 @@ void hexval_emul_exact_device(const double* pts, int64_t n, int mode, int max_de
 {
     for (int64_t i = 0; i < n; ++i)
         out[i] = mode == 2 ? exact_device_quad(pts + 8 * i) : exact_device_hex(pts + 24 * i, max_depth, mode == 1);
+    // exact subdivision where the device tier asks for it, as k_exact_dfs
+    std::vector<IW> st((size_t)(max_depth + 1) * kExactDfsWords);
+    for (int64_t i = 0; i < n; ++i)
+        if (mode == 0 && out[i] == kExactSubdivide) out[i] = exact_device_verdict(pts + 24 * i, max_depth, st.data());
 }
 
 // The host exact tier: mode 0 verdict, 1 corner-only test, 2 quadrangle.

@@ -63,6 +63,34 @@ def test_verdicts_on_scaled_near_degenerate_hexes(E):
     assert (_run(E, "hexval_emul_exact_device", wide, 0) == HOST).all()
 
 
+def test_exact_subdivision_settled_on_the_device(E):
+    # integer hexes whose top-level coefficients are not all positive (exact
+    # UNDECIDED at cap 0) need exact subdivision: the 384-bit depth-first
+    # tier decides every one of them on the device, with the rational
+    # answer of the oracle, and agrees with the host tier's big integers
+    P = _degenerate_integer_hexes(4000, 7)
+    cap0 = _run(E, "hexval_emul_exact_device", P, 0, max_depth=0)
+    need = np.nonzero(cap0 == 2)[0]
+    assert need.size > 20
+    for depth in (1, 3, 6):
+        dev = _run(E, "hexval_emul_exact_device", P[need], 0, max_depth=depth)
+        assert (dev != HOST).all(), depth
+        want = [exact.validity(P[e], max_depth=depth)["verdict"] for e in need]
+        assert list(dev) == want, depth
+        host = _run(E, "hexval_emul_exact_host", P[need], 0, max_depth=depth)
+        assert np.array_equal(dev, host), depth
+    # the sheared prisms (min J = eps at a non-dyadic point) to the largest
+    # cap: their closed-form verdicts (VALID once the sub-boxes are small
+    # enough for eps > 0, INVALID for eps < 0, UNDECIDED at caps reached
+    # first, and for eps = 0)
+    from tests.test_gpu_parity import _prism
+    cases = [(0.25, 6, 1), (2.0 ** -10, 6, 1), (-(2.0 ** -10), 6, 0), (2.0 ** -20, 6, 2),
+             (-(2.0 ** -20), 6, 2), (0.0, 6, 2), (2.0 ** -20, 20, 1), (-(2.0 ** -20), 20, 0)]
+    for eps, depth, want in cases:
+        dev = _run(E, "hexval_emul_exact_device", _prism(eps)[None], 0, max_depth=depth)
+        assert dev[0] == want, (eps, depth, dev[0])
+
+
 def test_depth_cap_zero_gives_undecided_exactly(E):
     P, _ = __import__("tests.test_oracle_pins", fromlist=["_twisted"])._twisted(120)
     dev = _run(E, "hexval_emul_exact_device", P[None], 0, max_depth=0)
