@@ -596,7 +596,9 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     // A single mesh with trusted connectivity may walk columns of stacked
     // elements (k_top_f64_walk, k_filter_f32_walk): the tuned choice, unless
     // the options fix it
-    const bool walk_able = !batched && gather == 2;
+    // (meshes of fewer than 8 layers of the smallest stride walked are not
+    // searched: the search costs more than the walk could save there)
+    const bool walk_able = !batched && gather == 2 && total >= 8 * kWalkMinStride;
     if (o.walk_layers) choice.walk = o.walk_layers > 0 ? o.walk_layers : 0;
     int walk_now = walk_able ? choice.walk : 0;   // layers of the pass being launched
     bool walk = walk_now > 0;
@@ -869,7 +871,7 @@ int run_min_jacobian(const hexval_mesh_t* mesh, const hexval_opts_t* opts_in, do
     const bool timing = st && st->timing;
     // the first round over a trusted mesh walks columns of stacked elements
     // (k_minj_top_walk) unless the options ask for plain tiles
-    const bool walk = mesh->connectivity && !o.validate_indices && o.walk_layers >= 0;
+    const bool walk = mesh->connectivity && !o.validate_indices && o.walk_layers >= 0 && n >= 8 * kWalkMinStride;
     const int64_t walk_limit = std::min<int64_t>(n, kWalkSearch);
 
     // Rounds: a round subdivides at most root_cap elements (a quarter of the

@@ -35,7 +35,8 @@ def check_layout(torch, V, C, label, expect_stride=None, precisions=(hx.FP64, hx
         for walk in (16, 3, 64):
             v, m, st = run(torch, V, C, walk, prec)
             say(f"{label} precision {prec} walk {walk}: stride {st['walk_stride']}, rounds {st['n_rounds']}")
-            assert st["walk_layers"] == walk
+            # meshes of fewer than 8 layers of the smallest stride are not searched
+            assert st["walk_layers"] == (walk if C.shape[0] >= 8 * 4096 else 0)
             assert st["n_recheck"] == st0["n_recheck"], "FP32 filter decisions differ"
             if expect_stride is not None:
                 assert st["walk_stride"] == expect_stride
