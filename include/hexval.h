@@ -22,8 +22,8 @@
  *   - verdicts are those of the algorithm in EXACT arithmetic: every FP64
  *     (or FP32) sign decision is checked against a rigorous error bound and
  *     the few elements whose decisions cannot be certified are recomputed in
- *     integer arithmetic (on the device when no exact subdivision is needed,
- *     else on host threads);
+ *     integer arithmetic, subdivision included, on the device (on host
+ *     threads for coordinates spanning more than 78 bits);
  *   - min_coeff is the minimum of the 27 top-level coefficients (a lower
  *     bound of min J by the convex-hull property of Section 3.1), NaN for
  *     BAD_INPUT.  Computed in FP64 it is within 256 u M^ of the exact
@@ -113,13 +113,14 @@ typedef struct {
     float ms_total;        /* device time from first launch to last kernel */
     int32_t block_threads; /* first-pass block size used (tuned or given) */
     int32_t n_exact_host;  /* of n_exact: elements the device exact tier left to
-                              the host (exact subdivision or a coordinate span
-                              over 78 bits) */
+                              the host (a coordinate span over 78 bits, or a
+                              subdivision store too small for one path) */
     int64_t grid_blocks;   /* first-pass grid used */
     int32_t walk_layers;   /* layers per column tile of the first pass (0: plain
                               tiles) */
     int32_t reserved;
-    int64_t walk_stride;   /* stack stride found for the column walk (0: none) */
+    int64_t walk_stride;   /* single mesh: stack stride found for the column
+                              walk (0: none; batches report 0) */
 } hexval_stats_t;
 
 /* Options.  Use hexval_opts_default() and change fields. */
@@ -137,13 +138,18 @@ typedef struct {
                                  to a multiple of 8) */
     void* stream;             /* hipStream_t to run on; NULL = the null stream */
     hexval_stats_t* stats;    /* optional output */
-    int32_t walk_layers;      /* single mesh with trusted connectivity: the first
-                                 pass checks columns of elements stacked with the
-                                 stride it finds (element e + s has as corners 0..3
-                                 the corners 4..7 of element e), loading each
-                                 shared face once; this many layers per column
-                                 tile.  0 = tuned (default), -1 = plain tiles,
-                                 1..64 = this many.  Results never depend on it */
+    int32_t walk_layers;      /* trusted connectivity (a single mesh, or an
+                                 FP64 batch whose meshes all have it): the first
+                                 pass checks columns of elements stacked with
+                                 the stride it finds per mesh (element e + s
+                                 has as corners 0..3 the corners 4..7 of
+                                 element e), loading each shared face once;
+                                 this many layers per column tile.  Meshes
+                                 under 32768 elements, or with a stride under
+                                 4096 or fewer than 8 layers of it in a batch,
+                                 take plain tiles.  0 = tuned (default), -1 =
+                                 plain tiles, 1..64 = this many.  Results
+                                 never depend on it */
     int32_t reserved;         /* must be 0 */
 } hexval_opts_t;
 

@@ -59,9 +59,19 @@ struct alignas(256) Counters {
     unsigned long long walk_code;     // stack stride of a single mesh: limit - stride, 0 = none
     unsigned long long walk_break;    // 2^62 - first layer whose column 0 breaks the stack, 0 = none
     unsigned long long n_rechecked;   // FP32 filter: elements redone in FP64 inside the pass
-    unsigned long long pad[1];
+    unsigned long long walk_tiles;    // tiles of a batched walking pass (set on the device)
     // first-pass tile counters, one per XCD chunk, each on a 256-byte line
     unsigned long long tile_next[8 * 32];
+};
+
+// Column walk of one mesh of a batch (set on the device before the walking
+// pass): stride s (0: the mesh is checked in plain tiles), layers walked, and
+// the mesh's first tile and tile count in the walking pass's numbering.
+struct WalkMesh {
+    int64_t s;
+    int64_t nl;
+    int64_t tile_begin;
+    int64_t n_tiles;
 };
 
 struct QueueDev {

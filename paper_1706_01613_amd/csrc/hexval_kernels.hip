@@ -654,23 +654,33 @@ struct WalkShape {
     int64_t n_walk;   // walk tiles
     int64_t tail;     // first element of the tail
     int64_t n_tiles;
+    WalkShape() = default;
+    // A single mesh: the stride and break found by k_walk_detect / k_walk_extent.
     __device__ WalkShape(int64_t n, const Counters* c, int64_t limit, int walk_layers)
     {
         const unsigned long long code = c->walk_code, brk = c->walk_break;
-        s = code ? limit - (int64_t)code : 0;
+        const int64_t st = code ? limit - (int64_t)code : 0;
+        int64_t l = 0;
+        if (st >= kWalkMinStride && st < n) l = brk ? (int64_t)(kWalkBreakBase - brk) : (n + st - 1) / st;
+        init(n, st, l, walk_layers, blockDim.x);
+    }
+    // Stride st with walked layers l (st = 0 or l = 0: plain tiles only), in
+    // tiles of `block` columns.
+    __host__ __device__ void init(int64_t n, int64_t st, int64_t l, int walk_layers, int64_t block)
+    {
+        s = st;
         layers = walk_layers;
-        if (s < kWalkMinStride || s >= n || layers < 1) {
+        if (s < kWalkMinStride || s >= n || layers < 1 || l < 1) {
             s = n;
             nl = 0;
             layers = 1;
         } else {
-            const int64_t all = (n + s - 1) / s;
-            nl = (int32_t)(brk ? (int64_t)(kWalkBreakBase - brk) : all);
+            nl = (int32_t)l;
         }
-        ncb = (int32_t)((s + blockDim.x - 1) / blockDim.x);
+        ncb = (int32_t)((s + block - 1) / block);
         n_walk = (int64_t)ncb * ((nl + layers - 1) / layers);
         tail = (int64_t)nl * s < n ? (int64_t)nl * s : n;
-        n_tiles = n_walk + (n - tail + blockDim.x - 1) / blockDim.x;
+        n_tiles = n_walk + (n - tail + block - 1) / block;
     }
 };
 
@@ -824,6 +834,116 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         finish_element<EDGES>(m, 0, e, active, p, false, a.q, a.max_depth, pb, nullptr);
     });
     push_flush(pb, sub_list(a.q), a.q, m, nullptr);
+}
+
+// Walk record mi of the batch (set on the device by an earlier launch, read
+// only here), with scalar loads.
+__device__ __forceinline__ WalkMesh uniform_walk_record(const WalkMesh* wm, int mi)
+{
+    typedef __attribute__((address_space(4))) const int64_t* const_i64;
+    const const_i64 w = (const_i64)(wm + mi);
+    return {w[0], w[1], w[2], w[3]};
+}
+
+// Forgets this lane's carried face (the next element loads all 8 corners).
+__device__ __forceinline__ void carry_forget(CarrySlots& cs)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cs.id[k * 256 + threadIdx.x] = -1;
+}
+
+// walk_prefetch_loop over a batch: tile t of the walking numbering belongs to
+// mesh tile_mesh[t] and is tile t - tile_begin of that mesh's WalkShape.
+// Vertex ids only mean something within one mesh, so each lane forgets its
+// carried face when a new tile starts.  body(m, mi, e, active, idx).
+template <typename Body>
+__device__ __forceinline__ void batch_walk_loop(const TopArgs& a, TileSched& ts, int4* stage, CarrySlots& cs,
+                                                Body body)
+{
+    const int wave_base = threadIdx.x & ~63;
+    typedef __attribute__((address_space(4))) const int32_t* const_i32;
+    auto prefetch = [&](const MeshDev& m, int64_t e) {
+        e = e < m.n ? e : m.n - 1;    // past the end: a valid row of the same mesh, ignored
+        const int* src = m.conn + 8 * e;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            __builtin_amdgcn_global_load_lds(src + 4 * h, (lds_ptr)&stage[h * 256 + wave_base], 16, 0, 0);
+    };
+    WalkShape ws;
+    WalkPos pos;
+    auto enter = [&](int64_t t, MeshDev& m, int& mi) {
+        mi = ((const_i32)a.tile_mesh)[(int64_t)uniform_u64((uint64_t)t)];
+        m = uniform_mesh_record(a.meshes, mi);
+        const WalkMesh w = uniform_walk_record(a.walk_meshes, mi);
+        ws.init(m.n, w.s, w.nl, a.walk_layers, blockDim.x);
+        pos.start(ws, t - w.tile_begin);
+    };
+    int mi = 0;
+    MeshDev m{};
+    int64_t t = ts.next_tile();
+    if (t >= 0) {
+        enter(t, m, mi);
+        prefetch(m, pos.base + threadIdx.x);
+    }
+    carry_forget(cs);
+    wait_vmem();
+    while (t >= 0) {
+        int idx[8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int4 c = stage[h * 256 + threadIdx.x];
+            idx[4 * h] = c.x;
+            idx[4 * h + 1] = c.y;
+            idx[4 * h + 2] = c.z;
+            idx[4 * h + 3] = c.w;
+        }
+        const int64_t e = pos.base + threadIdx.x;
+        const bool active = (int64_t)threadIdx.x < pos.cols && e < m.n;
+        // the next step: the layer above in the same tile, else the next tile
+        int mi_n = mi;
+        MeshDev mn = m;
+        bool fresh = false;
+        if (pos.left > 1) {
+            pos.base += ws.s;
+            --pos.left;
+        } else {
+            t = ts.next_tile();
+            if (t >= 0) {
+                enter(t, mn, mi_n);
+                fresh = true;
+            }
+        }
+        wait_lds();                    // the slots are free: every lane has read its row
+        issue_priority();
+        if (t >= 0) prefetch(mn, pos.base + threadIdx.x);
+        else prefetch(m, e);
+        body(m, mi, e, active, idx);
+        if (fresh) carry_forget(cs);
+        m = mn;
+        mi = mi_n;
+    }
+}
+
+// k_top_f64_batch_conn with the column walk of each stacked mesh.  (A batched
+// FP32 filter does not walk: its plain pass runs 4 waves per SIMD, which the
+// carried face's LDS would cut to 3, and rechecking in FP64 inside the pass
+// costs whole waves when the elements FP32 cannot decide are scattered, as
+// in meshes whose every vertex is jittered.)
+template <bool EDGES>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_top_f64_batch_walk(TopArgs a)
+{
+    __shared__ int4 stage[2 * 256];
+    __shared__ CarrySlots cs;
+    HX_PUSH_STORAGE;
+    TileSched ts((int64_t)a.q.cnt->walk_tiles, a.xcds, a.q.cnt);
+    batch_walk_loop(a, ts, stage, cs, [&](const MeshDev& m, int mi, int64_t e, bool active, const int* idx) {
+        V3 p[8];
+        const bool hit = carry_issue(m.points, idx, cs, p);
+        wait_loads();
+        carry_finish(idx, hit, cs, p);
+        finish_element<EDGES>(m, mi, e, active, p, false, a.q, a.max_depth, pb, a.meshes);
+    });
+    push_flush(pb, sub_list(a.q), a.q, a.mesh, a.meshes);
 }
 
 // k_top_f64_range for a batch whose meshes all have trusted connectivity,
@@ -2067,6 +2187,117 @@ __global__ void k_tile_table(const MeshDev* meshes, int n_meshes, int tile, int3
     }
 }
 
+// Per mesh of a batch (one block each): the stack stride among the first
+// n / 8 elements (so that at least 8 layers are walked), 1024 rows a step,
+// and the first layer whose column 0 does not sit on the one below, as
+// k_walk_detect and k_walk_extent find them for a single mesh.
+__global__ __launch_bounds__(256) void k_batch_walk_detect(const MeshDev* meshes, int n_meshes, WalkMesh* wm)
+{
+    __shared__ unsigned long long found, brk;
+    for (int mi = blockIdx.x; mi < n_meshes; mi += gridDim.x) {
+        const MeshDev m = meshes[mi];
+        int64_t s = 0, nl = 0;
+        if (m.conn && m.n >= 8 * kWalkMinStride) {           // the same in every thread of the block
+            const int32_t* conn = m.conn;
+            const int t0 = conn[4], t1 = conn[5], t2 = conn[6], t3 = conn[7];
+            const int64_t limit = m.n / 8 + 1 < kWalkSearch ? m.n / 8 + 1 : kWalkSearch;
+            if (threadIdx.x == 0) found = (unsigned long long)limit;
+            __syncthreads();
+            for (int64_t e0 = 1; e0 < limit; e0 += 4 * blockDim.x) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int64_t e = e0 + k * (int64_t)blockDim.x + threadIdx.x;
+                    if (e < limit) {
+                        const int32_t* b = conn + 8 * e;
+                        if (b[0] == t0 && b[1] == t1 && b[2] == t2 && b[3] == t3)
+                            atomicMin(&found, (unsigned long long)e);
+                    }
+                }
+                __syncthreads();
+                const bool done = found < (unsigned long long)limit;
+                __syncthreads();
+                if (done) break;
+            }
+            s = (int64_t)found;
+            if (s >= kWalkMinStride && s < limit) {
+                const int64_t all = (m.n + s - 1) / s;
+                if (threadIdx.x == 0) brk = (unsigned long long)all;
+                __syncthreads();
+                for (int64_t l0 = 1; l0 < all; l0 += blockDim.x) {
+                    const int64_t l = l0 + threadIdx.x;
+                    if (l < all) {
+                        const int32_t* lo = conn + 8 * ((l - 1) * s);
+                        const int32_t* up = conn + 8 * (l * s);
+                        if (up[0] != lo[4] || up[1] != lo[5] || up[2] != lo[6] || up[3] != lo[7])
+                            atomicMin(&brk, (unsigned long long)l);
+                    }
+                    __syncthreads();
+                    const bool done = brk < (unsigned long long)all;
+                    __syncthreads();
+                    if (done) break;
+                }
+                nl = (int64_t)brk;
+            } else {
+                s = 0;
+            }
+        }
+        if (threadIdx.x == 0) {
+            wm[mi].s = s;
+            wm[mi].nl = nl;
+        }
+        __syncthreads();   // found and brk are set again for the next mesh
+    }
+}
+
+// One block of 1024 threads: each mesh's tile count in the walking pass
+// (plain tiles where walking would take more tiles than plain ones), their
+// exclusive prefix sums as the meshes' first tiles, and the total.
+__global__ __launch_bounds__(1024) void k_batch_walk_tiles(const MeshDev* meshes, int n_meshes, int block,
+                                                           int layers, WalkMesh* wm, Counters* c)
+{
+    __shared__ int64_t part[1024];
+    const int per = (n_meshes + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int m0 = (int)threadIdx.x * per;
+    const int m1 = m0 + per < n_meshes ? m0 + per : n_meshes;
+    int64_t sum = 0;
+    for (int mi = m0; mi < m1; ++mi) {
+        const int64_t n = meshes[mi].n;
+        WalkShape ws;
+        ws.init(n, wm[mi].s, wm[mi].nl, layers, block);
+        const int64_t plain = (n + block - 1) / block;
+        int64_t nt = ws.n_tiles;
+        if (ws.nl == 0 || nt > plain) {
+            wm[mi].s = 0;
+            wm[mi].nl = 0;
+            nt = plain;
+        }
+        wm[mi].n_tiles = nt;
+        sum += nt;
+    }
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {   // inclusive scan
+        const int64_t v = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t begin = part[threadIdx.x] - sum;
+    for (int mi = m0; mi < m1; ++mi) {
+        wm[mi].tile_begin = begin;
+        begin += wm[mi].n_tiles;
+    }
+    if (threadIdx.x == blockDim.x - 1) c->walk_tiles = (unsigned long long)part[threadIdx.x];
+}
+
+__global__ void k_batch_walk_table(int n_meshes, const WalkMesh* wm, int32_t* tile_mesh)
+{
+    for (int mi = blockIdx.x; mi < n_meshes; mi += gridDim.x) {
+        const int64_t b = wm[mi].tile_begin, nt = wm[mi].n_tiles;
+        for (int64_t t = threadIdx.x; t < nt; t += blockDim.x) tile_mesh[b + t] = mi;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_collect_deferred(CollectArgs a)
 {
     for (int mi = 0; mi < a.n_meshes; ++mi) {
@@ -2142,7 +2373,9 @@ void launch_top_range(const TopArgs& a, bool batched, int grid, int block, hipSt
 {
     const bool edges = a.max_depth == 0;
     if (batched) {
-        if (a.batch_conn && edges) HX_LAUNCH((k_top_f64_batch_conn<true>), grid, block, s, a);
+        if (a.batch_conn && a.walk_layers && edges) HX_LAUNCH((k_top_f64_batch_walk<true>), grid, block, s, a);
+        else if (a.batch_conn && a.walk_layers) HX_LAUNCH((k_top_f64_batch_walk<false>), grid, block, s, a);
+        else if (a.batch_conn && edges) HX_LAUNCH((k_top_f64_batch_conn<true>), grid, block, s, a);
         else if (a.batch_conn) HX_LAUNCH((k_top_f64_batch_conn<false>), grid, block, s, a);
         else if (edges) HX_LAUNCH((k_top_f64_range<true, true, kGatherAny>), grid, block, s, a);
         else HX_LAUNCH((k_top_f64_range<true, false, kGatherAny>), grid, block, s, a);
@@ -2196,6 +2429,14 @@ void launch_walk_detect(const int32_t* conn, int64_t n, int64_t limit, Counters*
     const int64_t g = (limit + 255) / 256;
     HX_LAUNCH(k_walk_detect, g < 1024 ? g : 1024, 256, s, conn, limit, c);
     HX_LAUNCH(k_walk_extent, 64, 256, s, conn, n, limit, c);
+}
+void launch_batch_walk(const MeshDev* meshes, int n_meshes, int block, int layers, WalkMesh* wm,
+                       int32_t* tile_mesh, Counters* c, hipStream_t s)
+{
+    const int g = n_meshes < 4096 ? n_meshes : 4096;
+    HX_LAUNCH(k_batch_walk_detect, g, 256, s, meshes, n_meshes, wm);
+    HX_LAUNCH(k_batch_walk_tiles, 1, 1024, s, meshes, n_meshes, block, layers, wm, c);
+    HX_LAUNCH(k_batch_walk_table, g, 256, s, n_meshes, wm, tile_mesh);
 }
 void launch_tile_table(const MeshDev* meshes, int n_meshes, int tile, int32_t* tile_mesh, hipStream_t s)
 {

@@ -17,8 +17,9 @@ struct TopArgs {
     int32_t max_depth;
     int32_t xcds;                         // tile chunks (1 or 8)
     int32_t batch_conn;                   // batched: every mesh with tiles has trusted connectivity
-    int32_t walk_layers;                  // single trusted mesh: layers per column tile (0: no walk)
+    int32_t walk_layers;                  // trusted connectivity: layers per column tile (0: no walk)
     int64_t walk_limit;                   // elements searched for the stack stride (see k_walk_detect)
+    const WalkMesh* walk_meshes;          // batched walk: per-mesh strides and tile ranges
 };
 
 struct LevelArgs {
@@ -136,6 +137,15 @@ constexpr int kWalkLayers = 16;
 // idle).
 constexpr int64_t kWalkMinStride = 4096;
 void launch_walk_detect(const int32_t* conn, int64_t n, int64_t limit, Counters* c, hipStream_t s);
+// The same for every mesh of a batch of trusted meshes (each searched among
+// its first n / 8 elements, at most kWalkSearch; meshes below
+// 8 * kWalkMinStride elements are not walked), then the walking pass's tiles
+// of `block` columns and `layers` layers: per-mesh ranges in wm, the
+// tile -> mesh table in tile_mesh (at most one entry per plain tile of
+// `block` elements: a mesh that would need more tiles walking is checked in
+// plain tiles), their count in c->walk_tiles.  After launch_reset.
+void launch_batch_walk(const MeshDev* meshes, int n_meshes, int block, int layers, WalkMesh* wm,
+                       int32_t* tile_mesh, Counters* c, hipStream_t s);
 void launch_filter_range(const TopArgs& a, bool batched, int grid, int block, hipStream_t s);
 void launch_top_list(const TopArgs& a, bool batched, int grid, int block, hipStream_t s);
 void launch_level(const LevelArgs& a, int grid, hipStream_t s);

@@ -149,6 +149,8 @@ Workspace::~Workspace()
     dfree(minj);
     dfree(minj_defer);
     dfree(tile_mesh);
+    dfree(walk_meshes);
+    dfree(walk_tile_mesh);
     for (auto& e : ev)
         if (e) hipEventDestroy(e);
     if (prev >= 0) hipSetDevice(prev);
@@ -206,14 +208,18 @@ int Workspace::ensure(uint64_t want_nodes, uint64_t want_list, uint64_t want_mes
     if (want_meshes > mesh_cap) {
         dfree(meshes);
         hfree(h_meshes);
+        dfree(walk_meshes);
         mesh_cap = 0;
-        if ((rc = dalloc(&meshes, want_meshes)) || (rc = halloc(&h_meshes, want_meshes))) return rc;
+        if ((rc = dalloc(&meshes, want_meshes)) || (rc = halloc(&h_meshes, want_meshes)) ||
+            (rc = dalloc(&walk_meshes, want_meshes)))
+            return rc;
         mesh_cap = want_meshes;
     }
     if (want_tiles > tile_cap) {
         dfree(tile_mesh);
+        dfree(walk_tile_mesh);
         tile_cap = 0;
-        if ((rc = dalloc(&tile_mesh, want_tiles))) return rc;
+        if ((rc = dalloc(&tile_mesh, want_tiles)) || (rc = dalloc(&walk_tile_mesh, want_tiles))) return rc;
         tile_cap = want_tiles;
     }
     return HEXVAL_OK;
@@ -239,7 +245,7 @@ int Workspace::ensure_minj(uint64_t slots, uint64_t elements)
 
 uint64_t Workspace::footprint(uint64_t nodes, uint64_t list, uint64_t meshes, uint64_t tiles)
 {
-    return nodes * (sizeof(Node) + 16) + list * 12 + meshes * sizeof(MeshDev) + tiles * 4 +
+    return nodes * (sizeof(Node) + 16) + list * 12 + meshes * (sizeof(MeshDev) + sizeof(WalkMesh)) + tiles * 8 +
            kExactCap * (12 + 24 * 8 + 1) + sizeof(Counters);
 }
 
@@ -573,9 +579,11 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     }
     const MeshDev* dmeshes = batched ? w.meshes : nullptr;
     int64_t n_tiles = 0;
+    int tile_block = 0;
     // Tiles of `blk` elements; for a batch the mesh table and the
     // tile -> mesh table are rebuilt on the device.
     auto setup_tiles = [&](int blk) -> int {
+        tile_block = blk;
         n_tiles = 0;
         for (int i = 0; i < n_meshes; ++i) {
             md[i].tile_begin = n_tiles;
@@ -593,12 +601,15 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     };
     const bool timing = st && st->timing && w.ev[0];   // workspaces without events do not time
     const int xcds = 8;
-    // A single mesh with trusted connectivity may walk columns of stacked
-    // elements (k_top_f64_walk, k_filter_f32_walk): the tuned choice, unless
-    // the options fix it
+    // A single mesh with trusted connectivity, or a batch of them, may walk
+    // columns of stacked elements (k_top_f64_walk, k_filter_f32_walk,
+    // k_top_f64_batch_walk): the tuned choice, unless the options fix it
     // (meshes of fewer than 8 layers of the smallest stride walked are not
     // searched: the search costs more than the walk could save there)
-    const bool walk_able = !batched && gather == 2 && total >= 8 * kWalkMinStride;
+    // (batches walk in FP64 only, see k_top_f64_batch_walk)
+    bool walk_able = !batched && gather == 2 && total >= 8 * kWalkMinStride;
+    for (int i = 0; batched && batch_conn && o.precision == HEXVAL_FP64 && i < n_meshes && !walk_able; ++i)
+        walk_able = meshes[i].n >= 8 * kWalkMinStride;
     if (o.walk_layers) choice.walk = o.walk_layers > 0 ? o.walk_layers : 0;
     int walk_now = walk_able ? choice.walk : 0;   // layers of the pass being launched
     bool walk = walk_now > 0;
@@ -606,7 +617,8 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         TopArgs ta{};
         ta.mesh = single;
         ta.meshes = dmeshes;
-        ta.tile_mesh = w.tile_mesh;
+        ta.tile_mesh = batched && walk ? w.walk_tile_mesh : w.tile_mesh;
+        ta.walk_meshes = batched && walk ? w.walk_meshes : nullptr;
         ta.n_tiles = n_tiles;
         ta.list_count = &w.cnt->n_list;
         ta.q = q;
@@ -614,14 +626,18 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         ta.xcds = xcds;
         ta.batch_conn = batch_conn ? 1 : 0;
         ta.walk_layers = walk ? walk_now : 0;
-        ta.walk_limit = walk ? std::min<int64_t>(total, kWalkSearch) : 0;
+        ta.walk_limit = walk && !batched ? std::min<int64_t>(total, kWalkSearch) : 0;
         return ta;
     };
-    // the column walk needs the stack stride of this mesh, found after each
-    // counter reset (the walking pass reads it on the device)
+    // the column walk needs the stack stride of this mesh (of each mesh of a
+    // batch, and the batch's walking tiles), found after each counter reset
+    // (the walking pass reads them on the device)
     auto reset = [&]() {
         launch_reset(w.cnt, s);
-        if (walk) launch_walk_detect(single.conn, total, std::min<int64_t>(total, kWalkSearch), w.cnt, s);
+        if (walk && batched)
+            launch_batch_walk(w.meshes, n_meshes, tile_block, walk_now, w.walk_meshes, w.walk_tile_mesh, w.cnt, s);
+        else if (walk)
+            launch_walk_detect(single.conn, total, std::min<int64_t>(total, kWalkSearch), w.cnt, s);
     };
     auto launch_first = [&](const TopArgs& ta, int64_t g, int blk) {
         if (o.precision == HEXVAL_FP32_FILTER) launch_filter_range(ta, batched, (int)g, blk, s);
@@ -752,7 +768,7 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
             st->n_rounds = round + 1;
             if (round == 0) {
                 st->n_elements = total;
-                if (walk && c.walk_code) {
+                if (walk && !batched && c.walk_code) {
                     // the stride the walking pass used (it walks none below kWalkMinStride)
                     const int64_t stride = std::min<int64_t>(total, kWalkSearch) - (int64_t)c.walk_code;
                     st->walk_stride = stride >= kWalkMinStride && stride < total ? stride : 0;

@@ -40,6 +40,8 @@ struct Workspace {
     MeshDev* meshes = nullptr;
     MeshDev* h_meshes = nullptr;
     int32_t* tile_mesh = nullptr;
+    WalkMesh* walk_meshes = nullptr;   // [mesh_cap] batched column walk: per-mesh strides and tiles
+    int32_t* walk_tile_mesh = nullptr; // [tile_cap] its tile -> mesh table
     uint64_t* minj = nullptr;     // min-J arrays: 5 x minj_cap (u[0..2], ufinal, lb)
     uint64_t minj_cap = 0;
     int64_t* minj_defer = nullptr;   // min-J deferred-element lists: 2 x defer_cap

@@ -134,3 +134,84 @@ def test_min_jacobian_walk_equals_plain_tiles():
     ref = oracle.min_jacobian(V, C, rtol=1e-3, max_depth=6)
     lo, hi, _ = res[16]
     assert not np.any((lo > ref["hi"]) | (ref["lo"] > hi)), "disjoint min J intervals"
+
+
+def batch_run(torch, meshes, walk, precision=hx.FP64, max_depth=6):
+    vs = [torch.empty(C.shape[0], dtype=torch.uint8, device="cuda") for _, C in meshes]
+    ms = [torch.empty(C.shape[0], dtype=torch.float64, device="cuda") for _, C in meshes]
+    descs = [hx.make_mesh(V, C) for V, C in meshes]
+    st = hx.hexval_stats_t()
+    opts = hx.make_opts(precision=precision, max_depth=max_depth, walk_layers=walk,
+                        stream=torch.cuda.current_stream(), stats=st)
+    hx.hexval_check_batched(descs, opts, vs, ms)
+    torch.cuda.synchronize()
+    return [v.cpu().numpy() for v in vs], [m.cpu().numpy() for m in ms], st
+
+
+def mixed_batch():
+    """Host arrays of a batch: walkable lattices (one cut inside a layer,
+    one with broken rows, one followed by near-degenerate hexes), and meshes
+    the walk must leave to plain tiles (permuted, small layers, too few
+    layers, tiny, empty)."""
+    V, C = lattice()
+    rng = np.random.default_rng(9)
+    Cb = C.copy()
+    rows = rng.choice(C.shape[0], C.shape[0] // 10, replace=False)
+    Cb[rows] = Cb[rng.integers(0, C.shape[0], rows.size)]
+    Vn, Cn = synth.append_independent(*synth.warped_lattice(75, 60, 12, seed=12, jitter_fraction=0.1),
+                                      synth.near_degenerate_hexes(5000, seed=13))
+    return [
+        (V, C),
+        synth.warped_lattice(64, 64, 9, seed=14, jitter_fraction=0.3),     # 9 layers of 4096
+        (V, C[: C.shape[0] - 1234]),
+        (V, Cb),
+        (Vn, Cn),
+        (V, C[np.random.default_rng(15).permutation(C.shape[0])]),
+        synth.warped_lattice(30, 30, 40, seed=16, jitter_fraction=0.1),     # layers of 900
+        synth.warped_lattice(80, 70, 6, seed=17, jitter_fraction=0.1),      # 6 layers
+        (V, C[:7]),
+        (V[:0], C[:0]),
+        synth.warped_lattice(100, 90, 10, seed=18, jitter_fraction=0.6),
+    ]
+
+
+@pytest.mark.parametrize("precision", [hx.FP64, hx.FP32_FILTER])
+def test_batched_walk_equals_plain_tiles_and_oracle(precision):
+    torch = torch_cuda()
+    host = mixed_batch()
+    meshes = [(to_dev(torch, V), to_dev(torch, C.astype(np.int32))) for V, C in host]
+    base_v, base_m, st0 = batch_run(torch, meshes, -1, precision)
+    assert st0.walk_layers == 0
+    for k, (V, C) in enumerate(host):
+        if C.shape[0]:
+            assert_parity(base_v[k], base_m[k] if precision == hx.FP64 else None, V, C,
+                          label=f"batched plain mesh {k}")
+    for walk in (16, 3, 64):
+        v, m, st = batch_run(torch, meshes, walk, precision)
+        say(f"batched walk {walk} precision {precision}: rechecks {st.n_recheck}, rounds {st.n_rounds}")
+        assert st.walk_layers == (walk if precision == hx.FP64 else 0)   # batches walk in FP64 only
+        assert st.walk_stride == 0
+        assert st.n_recheck == st0.n_recheck, "FP32 filter decisions differ"
+        for k in range(len(host)):
+            assert np.array_equal(v[k], base_v[k]), f"mesh {k}: walk {walk} verdicts differ from plain tiles"
+            assert np.array_equal(m[k].view(np.int64), base_m[k].view(np.int64)), f"mesh {k}: walk {walk} min_coeff"
+
+
+def test_batched_walk_depth_zero_and_tuned():
+    torch = torch_cuda()
+    host = mixed_batch()[:6]
+    meshes = [(to_dev(torch, V), to_dev(torch, C.astype(np.int32))) for V, C in host]
+    for prec in (hx.FP64, hx.FP32_FILTER):
+        base_v, base_m, _ = batch_run(torch, meshes, -1, prec, max_depth=0)
+        v, m, st = batch_run(torch, meshes, 16, prec, max_depth=0)
+        for k in range(len(host)):
+            assert np.array_equal(v[k], base_v[k]), f"cap 0 mesh {k}"
+        if prec == hx.FP64:
+            for k, (V, C) in enumerate(host):
+                assert_parity(v[k], m[k], V, C, max_depth=0, label=f"cap 0 mesh {k}")
+    # the tuner's choice (walk or not) never changes results
+    v, m, st = batch_run(torch, meshes, 0, hx.FP64)
+    base_v, base_m, _ = batch_run(torch, meshes, -1, hx.FP64)
+    for k in range(len(host)):
+        assert np.array_equal(v[k], base_v[k])
+        assert np.array_equal(m[k].view(np.int64), base_m[k].view(np.int64))
