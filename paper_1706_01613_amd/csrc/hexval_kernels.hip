@@ -1066,17 +1066,31 @@ __global__ __launch_bounds__(256) void k_filter_f32_conn(TopArgs a)
 // k_filter_f32_conn with the column walk, and the FP64 recheck in the same
 // pass: the carried face's LDS already limits the block count to what 168
 // registers allow, so the elements the FP32 pass cannot decide are redone in
-// FP64 from the corners still in registers (as finish_element decides them,
-// subdivision list included) instead of being listed and gathered again.
+// FP64 here (as finish_element decides them, subdivision list included)
+// instead of being listed for a second kernel.  A wave where most lanes need
+// it (a run of near-degenerate elements) redoes them at once from the corners
+// in its registers; scattered ones are kept in a per-wave LDS buffer and
+// redone 64 at a time, each lane gathering its element again, so that a few
+// uncertain lanes do not cost their wave a whole FP64 evaluation.  The count
+// goes out with one atomic per wave at the end.
+constexpr int kRecheckBuf = 128;
+constexpr int kRecheckInPlace = 48;   // uncertain lanes from which a wave redoes them at once
+
 template <bool EDGES>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_filter_f32_walk(TopArgs a)
 {
     __shared__ int4 stage[2 * 256];
     __shared__ CarrySlots cs;
+    __shared__ int64_t recheck_buf_[4 * kRecheckBuf];
     HX_PUSH_STORAGE;
     const MeshDev& m = a.mesh;
     const WalkShape ws(m.n, a.q.cnt, a.walk_limit, a.walk_layers);
     TileSched ts(ws.n_tiles, a.xcds, a.q.cnt);
+    const int lane = threadIdx.x & 63;
+    __attribute__((address_space(3))) int64_t* rbuf =
+        (__attribute__((address_space(3))) int64_t*)(recheck_buf_ + (threadIdx.x >> 6) * kRecheckBuf);
+    int rn = 0;                          // buffered elements (wave-uniform)
+    unsigned long long rechecked = 0;    // elements this wave redid in FP64 (wave-uniform)
     carry_clear(cs);
     walk_prefetch_loop(m.conn, m.n, ws, ts, stage, [&](int64_t e, bool active, const int* idx) {
         V3 p[8];
@@ -1090,16 +1104,52 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
             st = filter_state(r);
             mn = r.min27;
         }
-        const bool recheck = active && st < 0;
-        if (active && !recheck) {
+        bool redo = active && st < 0;
+        if (active && !redo) {
             *global(m.verdict + e) = (uint8_t)st;
             if (m.min_coeff) *global(m.min_coeff + e) = (double)mn;
         }
-        if (ballot(recheck)) {
-            wave_count(&a.q.cnt->n_rechecked, recheck);
-            finish_element<EDGES>(m, 0, e, recheck, p, false, a.q, a.max_depth, pb, nullptr);
+        const uint64_t rm = ballot(redo);
+        const int nr = __popcll(rm);
+        if (nr && nr < kRecheckInPlace) {
+            // scattered: buffered; once 64 are held, each lane takes one
+            // and gathers its corners again (in place of this step's)
+            if (redo) rbuf[rn + lane_rank(rm)] = e;
+            rn += nr;
+            redo = false;
+            if (rn >= 64) {
+                lds_order();             // the entries other lanes wrote are visible
+                e = rbuf[lane];
+                bool bad = false;
+                load_points_t<kGatherConn>(m, e, p, bad);
+                redo = true;
+                // the rest (fewer than kRecheckInPlace) to the front: reads
+                // from [64, rn), writes to [0, rn - 64), disjoint
+                int64_t rest = 0;
+                if (lane < rn - 64) rest = rbuf[64 + lane];
+                if (lane < rn - 64) rbuf[lane] = rest;
+                rn -= 64;
+            }
+        }
+        if (ballot(redo)) {
+            rechecked += (unsigned long long)__popcll(ballot(redo));
+            finish_element<EDGES>(m, 0, e, redo, p, false, a.q, a.max_depth, pb, nullptr);
         }
     });
+    if (rn) {
+        lds_order();
+        const bool on = lane < rn;
+        int64_t e = 0;
+        V3 p[8];
+        bool bad = false;
+        if (on) {
+            e = rbuf[lane];
+            load_points_t<kGatherConn>(m, e, p, bad);
+        }
+        rechecked += (unsigned long long)rn;
+        finish_element<EDGES>(m, 0, e, on, p, false, a.q, a.max_depth, pb, nullptr);
+    }
+    if (lane == 0 && rechecked) atomicAdd(&a.q.cnt->n_rechecked, rechecked);
     push_flush(pb, sub_list(a.q), a.q, m, nullptr);
 }
 

@@ -94,6 +94,17 @@ def test_stacked_part_then_independent_near_degenerate_hexes():
     check_layout(torch, V, C, "lattice + near-degenerate", expect_stride=NX * NY)
 
 
+def test_fp32_rechecks_scattered_over_the_mesh():
+    # every vertex jittered: the elements FP32 cannot decide are spread over
+    # many waves, which recheck them in FP64 in batches of 64 from a per-wave
+    # buffer (the waves where most lanes need it redo them in place)
+    torch = torch_cuda()
+    V, C = synth.warped_lattice(NX, NY, NZ, seed=19, jitter=0.45, jitter_all=True)
+    check_layout(torch, V, C, "scattered rechecks", expect_stride=NX * NY)
+    V2, C2 = synth.append_independent(V, C, synth.near_degenerate_hexes(20000, seed=20))
+    check_layout(torch, V2, C2, "scattered and clustered rechecks", expect_stride=NX * NY)
+
+
 def test_small_layers_are_not_walked():
     torch = torch_cuda()
     V, C = synth.warped_lattice(30, 30, 40, seed=7, jitter_fraction=0.1)   # 900 per layer
