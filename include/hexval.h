@@ -148,8 +148,11 @@ typedef struct {
                                  under 32768 elements, or with a stride under
                                  4096 or fewer than 8 layers of it in a batch,
                                  take plain tiles.  0 = tuned (default), -1 =
-                                 plain tiles, 1..64 = this many.  Results
-                                 never depend on it */
+                                 plain tiles, 1..64 = this many.  The same for
+                                 the rows of a quadrangle mesh with trusted
+                                 connectivity (quad e + s has as corners 0, 1
+                                 the corners 3, 2 of quad e; 0 = 16 rows).
+                                 Results never depend on it */
     int32_t reserved;         /* must be 0 */
 } hexval_opts_t;
 
@@ -246,7 +249,7 @@ int hexval_corner_test(const hexval_mesh_t* mesh, const hexval_opts_t* opts, uin
  *   [n_points,2] with connectivity device [n,4] int32; corners in the order
  *   (0,0) (1,0) (1,1) (0,1) of the reference square (counter-clockwise for a
  *   valid element in a right-handed plane); rows 16-byte aligned.
- * opts: validate_indices, stream, stats (NULL = defaults).
+ * opts: validate_indices, walk_layers, stream, stats (NULL = defaults).
  * verdicts: device [n] uint8 (HEXVAL_INVALID, HEXVAL_VALID, HEXVAL_BAD_INPUT).
  * min_j: device [n] float64 or NULL: min J = the smallest corner value
  *   (FP64; NaN for BAD_INPUT).

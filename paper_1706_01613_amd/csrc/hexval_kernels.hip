@@ -2181,6 +2181,73 @@ __global__ __launch_bounds__(256) void k_quad_check(CornerArgs a)
     }
 }
 
+// Quadrangles stacked in rows (quad e + r has as corners 0, 1 the corners
+// 3, 2 of quad e, r found by k_quad_walk_detect): each lane walks up its
+// column of quads, in the tiles of WalkShape, and keeps the shared edge's two
+// vertices in registers, so it loads 2 vertices per quad instead of 4.  The
+// ids decide whether the kept edge is the quad's first one, so any
+// connectivity gives the results of k_quad_check.
+__global__ __launch_bounds__(256) void k_quad_walk(CornerArgs a)
+{
+    const MeshDev& m = a.mesh;
+    const WalkShape ws(m.n, a.q.cnt, a.walk_limit, a.walk_layers);
+    TileSched ts(ws.n_tiles, a.xcds, a.q.cnt);
+    const int l = threadIdx.x;
+    int k0 = -1, k1 = -1;         // ids of the kept edge
+    double2 v0 = make_double2(0.0, 0.0), v1 = v0;
+    for (int64_t t = ts.next_tile(); t >= 0; t = ts.next_tile()) {
+        WalkPos pos;
+        pos.start(ws, t);
+        for (int r = 0; r < pos.left; ++r) {
+            const int64_t e = pos.base + (int64_t)r * ws.s + l;
+            const bool active = (int64_t)l < pos.cols && e < m.n;
+            double2 p[4];
+            if (active) {
+                const int4 c = *reinterpret_cast<const int4*>(m.conn + 4 * e);
+                const bool hit = c.x == k0 && c.y == k1;
+                p[2] = *reinterpret_cast<const double2*>(m.points + 2 * (int64_t)c.z);
+                p[3] = *reinterpret_cast<const double2*>(m.points + 2 * (int64_t)c.w);
+                if (hit) {
+                    p[0] = v0;
+                    p[1] = v1;
+                } else {
+                    p[0] = *reinterpret_cast<const double2*>(m.points + 2 * (int64_t)c.x);
+                    p[1] = *reinterpret_cast<const double2*>(m.points + 2 * (int64_t)c.y);
+                }
+                k0 = c.w;
+                k1 = c.z;
+                v0 = p[3];
+                v1 = p[2];
+            }
+            quad_element(a, e, active, p, false);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_quad_walk_detect(const int32_t* conn, int64_t limit, Counters* c)
+{
+    const int t0 = conn[3], t1 = conn[2];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < limit; e += stride) {
+        if ((int64_t)load_relaxed(&c->walk_code) > limit - e) return;
+        const int32_t* b = conn + 4 * e;
+        if (b[0] == t0 && b[1] == t1) atomicMax(&c->walk_code, (unsigned long long)(limit - e));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_quad_walk_extent(const int32_t* conn, int64_t n, int64_t limit, Counters* c)
+{
+    const unsigned long long code = c->walk_code;
+    const int64_t s = code ? limit - (int64_t)code : 0;
+    if (s < kWalkMinStride || s >= n) return;
+    const int64_t nl = (n + s - 1) / s;
+    for (int64_t l = 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < nl; l += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t* lo = conn + 4 * ((l - 1) * s);
+        const int32_t* up = conn + 4 * (l * s);
+        if (up[0] != lo[3] || up[1] != lo[2]) atomicMax(&c->walk_break, kWalkBreakBase - (unsigned long long)l);
+    }
+}
+
 // The 4 points (8 doubles) of each listed element, for the exact tier.
 __global__ void k_quad_gather(CornerArgs a, int64_t n, double* out)
 {
@@ -2522,7 +2589,17 @@ void launch_corner_test(const CornerArgs& a, int grid, hipStream_t s) { HX_LAUNC
 void launch_corner_collect(const CornerArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_corner_collect, grid, 256, s, a); }
 // (The quadrangle kernel needs about 50 registers, so occupancy already
 // hides its gather latency; the prefetching loop measured slower for it.)
-void launch_quad_check(const CornerArgs& a, int grid, hipStream_t s) { HX_LAUNCH(k_quad_check, grid, 256, s, a); }
+void launch_quad_check(const CornerArgs& a, int grid, hipStream_t s)
+{
+    if (a.walk_layers) HX_LAUNCH(k_quad_walk, grid, 256, s, a);
+    else HX_LAUNCH(k_quad_check, grid, 256, s, a);
+}
+void launch_quad_walk_detect(const int32_t* conn, int64_t n, int64_t limit, Counters* c, hipStream_t s)
+{
+    const int64_t g = (limit + 255) / 256;
+    HX_LAUNCH(k_quad_walk_detect, g < 1024 ? g : 1024, 256, s, conn, limit, c);
+    HX_LAUNCH(k_quad_walk_extent, 64, 256, s, conn, n, limit, c);
+}
 void launch_quad_gather(const CornerArgs& a, int64_t n, double* out, hipStream_t s)
 {
     const int64_t g = (n + 255) / 256;

@@ -111,6 +111,8 @@ struct CornerArgs {
     double* quality;     // [n] or nullptr
     int64_t n_tiles;
     int32_t xcds;
+    int32_t walk_layers; // quadrangles with trusted connectivity: rows per column tile (0: plain tiles)
+    int64_t walk_limit;  // quads searched for the row stride
 };
 
 void launch_corner_test(const CornerArgs& a, int grid, hipStream_t s);
@@ -118,6 +120,11 @@ void launch_corner_test(const CornerArgs& a, int grid, hipStream_t s);
 // `quality` carries min_j.
 void launch_quad_check(const CornerArgs& a, int grid, hipStream_t s);
 void launch_quad_gather(const CornerArgs& a, int64_t n, double* out, hipStream_t s);
+// Row stride of a quadrangle mesh with trusted connectivity (the smallest
+// r < limit with quad r's corners 0, 1 = quad 0's corners 3, 2) and the
+// first row whose quad 0 does not sit on the row below, into c->walk_code /
+// c->walk_break as launch_walk_detect does for hexahedra (after launch_reset).
+void launch_quad_walk_detect(const int32_t* conn, int64_t n, int64_t limit, Counters* c, hipStream_t s);
 void launch_corner_collect(const CornerArgs& a, int grid, hipStream_t s);
 
 void launch_minj_top(const MinjArgs& a, int grid, hipStream_t s);

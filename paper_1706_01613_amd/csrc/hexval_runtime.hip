@@ -1010,10 +1010,18 @@ static int run_corner_or_quad(const hexval_mesh_t* mesh, const hexval_opts_t* op
     a.quality = quality;
     a.n_tiles = (n + 255) / 256;
     a.xcds = 8;
+    // quadrangles with trusted connectivity walk their rows (k_quad_walk)
+    // unless the options ask for plain tiles
+    const bool walk = quad && mesh->connectivity && !o.validate_indices && o.walk_layers >= 0 &&
+                      n >= 8 * kWalkMinStride;
+    a.walk_layers = walk ? (o.walk_layers > 0 ? o.walk_layers : kWalkLayers) : 0;
+    a.walk_limit = std::min<int64_t>(n, kWalkSearch);
     const bool timing = st && st->timing;
     launch_reset(w.cnt, s);
+    if (walk) launch_quad_walk_detect(mesh->connectivity, n, a.walk_limit, w.cnt, s);
     if (timing) HX_HIP(hipEventRecord(w.ev[0], s));
-    const int grid = o.grid_blocks ? (int)std::max<int64_t>(8, (o.grid_blocks + 7) / 8 * 8) : cus * 8;
+    // 8 blocks per CU, 7 for the quadrangle walk (70 VGPRs: 7 waves per SIMD)
+    const int grid = o.grid_blocks ? (int)std::max<int64_t>(8, (o.grid_blocks + 7) / 8 * 8) : cus * (walk ? 7 : 8);
     if (quad) launch_quad_check(a, grid, s);
     else launch_corner_test(a, grid, s);
     if (timing) HX_HIP(hipEventRecord(w.ev[1], s));
@@ -1021,6 +1029,7 @@ static int run_corner_or_quad(const hexval_mesh_t* mesh, const hexval_opts_t* op
     HX_HIP(hipMemcpyAsync(w.hcnt, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
     HX_HIP(hipStreamSynchronize(s));
     uint64_t pending = w.hcnt->n_exact, settled = 0;
+    const uint64_t walk_code = w.hcnt->walk_code;
     int64_t on_host = 0;
     while (pending > 0) {
         const int64_t k = (int64_t)std::min<uint64_t>(pending, w.exact_cap);
@@ -1055,6 +1064,12 @@ static int run_corner_or_quad(const hexval_mesh_t* mesh, const hexval_opts_t* op
         st->n_exact = (int64_t)settled;
         st->n_exact_host = (int32_t)on_host;
         st->n_rounds = 1;
+        st->walk_layers = a.walk_layers;
+        if (walk && walk_code) {
+            // the row stride the walking pass used (it walks none below kWalkMinStride)
+            const int64_t stride = a.walk_limit - (int64_t)walk_code;
+            st->walk_stride = stride >= kWalkMinStride && stride < n ? stride : 0;
+        }
         if (timing) {
             hipEventElapsedTime(&st->ms_first_pass, w.ev[0], w.ev[1]);
             hipEventElapsedTime(&st->ms_total, w.ev[0], w.ev[2]);

@@ -328,7 +328,7 @@ def corner_test(points, connectivity=None, validate_indices=False, stream=None, 
 
 
 def quad_check(points, connectivity=None, validate_indices=False, stream=None, stats=False, want_min=True,
-               grid_blocks=0):
+               grid_blocks=0, walk_layers=0):
     """Allocate outputs and run hexval_quad_check.  points: [n,4,2] float64, or
     [m,2] with connectivity [n,4] int32.  Returns (verdicts, min_j or None,
     stats dict or None)."""
@@ -340,7 +340,7 @@ def quad_check(points, connectivity=None, validate_indices=False, stream=None, s
     st.timing = 1 if stats else 0
     if stream is None:
         stream = torch.cuda.current_stream(points.device)
-    opts = make_opts(FP64, 6, validate_indices, 0, 0, grid_blocks, stream, st)
+    opts = make_opts(FP64, 6, validate_indices, 0, 0, grid_blocks, stream, st, walk_layers)
     mesh = hexval_mesh_t(_addr(points), int(points.shape[0]) if connectivity is not None else 0,
                          _addr(connectivity), int(n))
     hexval_quad_check(mesh, opts, verdicts, min_j)

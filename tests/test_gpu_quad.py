@@ -71,3 +71,42 @@ def test_quad_closed_forms_and_bad_input():
     v, m, _ = _gpu(torch, P)
     assert list(v) == [hx.VALID, hx.VALID, hx.INVALID, hx.INVALID, hx.INVALID, hx.BAD_INPUT]
     assert m[0] == 1.0 and abs(m[1] - np.linalg.det(A)) < 1e-15 and np.isnan(m[5])
+
+
+def _walk_layouts():
+    """Quad lattices whose rows the walk follows (5000 quads a row), cut,
+    broken, permuted, and with integer coordinates (exact tier)."""
+    V, C = synth.quad_lattice(5000, 40, seed=6, jitter_fraction=0.2, jitter=0.6)
+    rng = np.random.default_rng(7)
+    Cb = C.copy()
+    rows = rng.choice(C.shape[0], C.shape[0] // 10, replace=False)
+    Cb[rows] = Cb[rng.integers(0, C.shape[0], rows.size)]
+    Cf = C.copy()
+    flip = rng.choice(C.shape[0], 300, replace=False)
+    Cf[flip] = Cf[flip][:, [3, 2, 1, 0]]
+    Vi, Ci = synth.quad_lattice(4200, 10, seed=8, amp=0.0, jitter_fraction=0.3, jitter=1.0)
+    Vi = np.rint(Vi)
+    return [("lattice", V, C, 5000), ("partial row", V, C[: C.shape[0] - 777], 5000), ("broken", V, Cb, None),
+            ("reflected", V, Cf, 5000), ("permuted", V, C[rng.permutation(C.shape[0])], None),
+            ("integer", Vi, Ci, 4200), ("tiny", V, C[:9], 0)]
+
+
+def test_quad_row_walk_equals_plain_tiles_and_oracle():
+    # each lane keeps the shared edge of the quads stacked in rows; any
+    # connectivity gives the plain pass's results bit for bit
+    torch = torch_cuda()
+    for label, V, C, stride in _walk_layouts():
+        C = np.ascontiguousarray(C.astype(np.int32))
+        bv, bm, bst = _gpu(torch, V, C, walk_layers=-1)
+        assert bst["walk_layers"] == 0
+        _compare(bv, bm, V, C, label=f"{label} plain")
+        for walk in (16, 3, 64):
+            v, m, st = _gpu(torch, V, C, walk_layers=walk)
+            _say(f"quads {label} walk {walk}: stride {st['walk_stride']}, exact {st['n_exact']}")
+            assert st["walk_layers"] == (walk if C.shape[0] >= 8 * 4096 else 0)
+            if stride is not None and C.shape[0] >= 8 * 4096:
+                assert st["walk_stride"] == stride, label
+            assert st["n_exact"] == bst["n_exact"]
+            assert np.array_equal(v, bv), f"{label}: walk {walk} verdicts differ from plain tiles"
+            assert np.array_equal(np.nan_to_num(m, nan=7.0).view(np.int64),
+                                  np.nan_to_num(bm, nan=7.0).view(np.int64)), f"{label}: walk {walk} min_j"
