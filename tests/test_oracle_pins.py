@@ -52,7 +52,18 @@ def test_fig6_valid_with_negative_coefficients():
 def test_fig7_invalid_with_good_corner_quality():
     P, expect = _ref.read_figure("fig7.txt")
     assert expect["verdict"] == ["INVALID"]
-    assert _one(P)["verdict"] == oracle.INVALID
+    r = _one(P)
+    assert r["verdict"] == oracle.INVALID
+    # decided among the 20 sampled values (Section 6 step 2): the 8 corner
+    # values are positive and the witness, an edge midpoint, has J <= 0, both
+    # by exact shape-function arithmetic independent of the oracle
+    Pf = [tuple(Fraction(float(x)) for x in p) for p in P]
+    corners = [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)]
+    assert all(_ref.jacobian_shape(Pf, *c) > 0 for c in corners)
+    assert r["level"] == 0 and r["nodes"] == 0
+    w = [Fraction(float(x)) for x in r["witness"]]
+    assert sorted(x == Fraction(1, 2) for x in w) == [False, False, True]   # an edge midpoint
+    assert _ref.jacobian_shape(Pf, *w) <= 0
     # minimum scaled Jacobian over the 8 corners, Section 7: printed 0.64
     lo, hi = (float(x) for x in expect["corner_scaled_jacobian_min"])
     nbr = {0: (1, 3, 4), 1: (2, 0, 5), 2: (3, 1, 6), 3: (0, 2, 7),

@@ -50,11 +50,16 @@ def test_corner_relation_j1_plus_j3_equals_j2_plus_j4():
     # Section 2.1 (the areas of the corner triangles); exact on dyadic input.
     # The relation holds for the corner values, which also shows the corner
     # to which each of the four products belongs.
+    # The oracle's min J is the smallest of these values (exact here: dyadic
+    # coordinates with few bits), and its verdict their sign.
     rng = np.random.default_rng(3)
     for _ in range(200):
         P = SQ + rng.integers(-8, 9, size=(4, 2)) / 16.0
         J = _corner_values_exact(P)
         assert J[0] + J[2] == J[1] + J[3]
+        v, m = _q(P)
+        assert m == float(min(J))
+        assert v == (oracle.VALID if min(J) > 0 else oracle.INVALID)
 
 
 def test_reflection_and_bow_tie_and_reflex_corner_are_invalid():
