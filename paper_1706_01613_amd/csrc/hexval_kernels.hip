@@ -1091,8 +1091,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         (__attribute__((address_space(3))) int64_t*)(recheck_buf_ + (threadIdx.x >> 6) * kRecheckBuf);
     int rn = 0;                          // buffered elements (wave-uniform)
     unsigned long long rechecked = 0;    // elements this wave redid in FP64 (wave-uniform)
+    // FP64 decisions of the first `count` buffered elements, one per lane
+    auto recheck_buffered = [&](int count) {
+        lds_order();                     // the entries other lanes wrote are visible
+        const bool on = lane < count;
+        int64_t eb = 0;
+        V3 q[8];
+        bool bad = false;
+        if (on) {
+            eb = rbuf[lane];
+            load_points_t<kGatherConn>(m, eb, q, bad);
+        }
+        finish_element<EDGES>(m, 0, eb, on, q, false, a.q, a.max_depth, pb, nullptr);
+        rechecked += (unsigned long long)count;
+    };
     carry_clear(cs);
     walk_prefetch_loop(m.conn, m.n, ws, ts, stage, [&](int64_t e, bool active, const int* idx) {
+        if (rn >= 64) {
+            // a full batch of buffered elements, before this element's corners
+            // are loaded; the rest (fewer than kRecheckInPlace) to the front:
+            // reads from [64, rn), writes to [0, rn - 64), disjoint
+            recheck_buffered(64);
+            int64_t rest = 0;
+            if (lane < rn - 64) rest = rbuf[64 + lane];
+            if (lane < rn - 64) rbuf[lane] = rest;
+            rn -= 64;
+        }
         V3 p[8];
         const bool hit = carry_issue(m.points, idx, cs, p);
         wait_loads();
@@ -1104,51 +1128,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
             st = filter_state(r);
             mn = r.min27;
         }
-        bool redo = active && st < 0;
-        if (active && !redo) {
+        const bool recheck = active && st < 0;
+        if (active && !recheck) {
             *global(m.verdict + e) = (uint8_t)st;
             if (m.min_coeff) *global(m.min_coeff + e) = (double)mn;
         }
-        const uint64_t rm = ballot(redo);
+        const uint64_t rm = ballot(recheck);
         const int nr = __popcll(rm);
-        if (nr && nr < kRecheckInPlace) {
-            // scattered: buffered; once 64 are held, each lane takes one
-            // and gathers its corners again (in place of this step's)
-            if (redo) rbuf[rn + lane_rank(rm)] = e;
+        if (nr >= kRecheckInPlace) {
+            // most lanes: at once, from the corners in registers
+            rechecked += (unsigned long long)nr;
+            finish_element<EDGES>(m, 0, e, recheck, p, false, a.q, a.max_depth, pb, nullptr);
+        } else if (nr) {
+            // scattered: buffered, redone 64 at a time
+            if (recheck) rbuf[rn + lane_rank(rm)] = e;
             rn += nr;
-            redo = false;
-            if (rn >= 64) {
-                lds_order();             // the entries other lanes wrote are visible
-                e = rbuf[lane];
-                bool bad = false;
-                load_points_t<kGatherConn>(m, e, p, bad);
-                redo = true;
-                // the rest (fewer than kRecheckInPlace) to the front: reads
-                // from [64, rn), writes to [0, rn - 64), disjoint
-                int64_t rest = 0;
-                if (lane < rn - 64) rest = rbuf[64 + lane];
-                if (lane < rn - 64) rbuf[lane] = rest;
-                rn -= 64;
-            }
-        }
-        if (ballot(redo)) {
-            rechecked += (unsigned long long)__popcll(ballot(redo));
-            finish_element<EDGES>(m, 0, e, redo, p, false, a.q, a.max_depth, pb, nullptr);
         }
     });
-    if (rn) {
-        lds_order();
-        const bool on = lane < rn;
-        int64_t e = 0;
-        V3 p[8];
-        bool bad = false;
-        if (on) {
-            e = rbuf[lane];
-            load_points_t<kGatherConn>(m, e, p, bad);
-        }
-        rechecked += (unsigned long long)rn;
-        finish_element<EDGES>(m, 0, e, on, p, false, a.q, a.max_depth, pb, nullptr);
-    }
+    if (rn) recheck_buffered(rn);
     if (lane == 0 && rechecked) atomicAdd(&a.q.cnt->n_rechecked, rechecked);
     push_flush(pb, sub_list(a.q), a.q, m, nullptr);
 }
