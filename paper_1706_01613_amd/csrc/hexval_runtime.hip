@@ -514,6 +514,7 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     // Launch shape of the first pass: explicit options, else the tuning cache,
     // else (autotuning on) measured below on this input, else defaults.
     TuneChoice choice;
+    bool tuned = false;   // choice from the tuning cache or measured on this call
     // a batch whose non-empty meshes all have trusted connectivity takes the
     // prefetching first pass (its own tuning key)
     bool batch_conn = batched && !o.validate_indices;
@@ -529,7 +530,10 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load_locked();
         auto it = g_tune.find(key);
-        if (it != g_tune.end()) choice = it->second;
+        if (it != g_tune.end()) {
+            choice = it->second;
+            tuned = true;
+        }
         else need_tune = tune && autotune_enabled();
     }
     // Automatic queue size: 1/32 of the elements, at least 2^19 nodes (any
@@ -611,6 +615,10 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
     for (int i = 0; batched && batch_conn && o.precision == HEXVAL_FP64 && i < n_meshes && !walk_able; ++i)
         walk_able = meshes[i].n >= 8 * kWalkMinStride;
     if (o.walk_layers) choice.walk = o.walk_layers > 0 ? o.walk_layers : 0;
+    // an untuned batch (the server's calls) checks in plain tiles: the
+    // per-mesh stride search costs more than the walk saves on most batches
+    // of small meshes
+    else if (batched && !tuned && !need_tune) choice.walk = 0;
     int walk_now = walk_able ? choice.walk : 0;   // layers of the pass being launched
     bool walk = walk_now > 0;
     auto first_args = [&]() {
@@ -661,8 +669,9 @@ int run_check_ws(const hexval_mesh_t* meshes, int n_meshes, bool batched, const 
                 const int64_t g = grid_for(c, n_tiles, cus);
                 float ms = 0.0f;
                 for (int rep = 0; rep < 2; ++rep) {
-                    reset();
+                    // the walk's stride search is part of what a candidate costs
                     HX_HIP(hipEventRecord(w.ev[0], s));
+                    reset();
                     launch_first(first_args(), g, blk);
                     HX_HIP(hipEventRecord(w.ev[1], s));
                     HX_HIP(hipGetLastError());
