@@ -1145,7 +1145,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
             rn += nr;
         }
     });
-    if (rn) recheck_buffered(rn);
+    // what the last steps left (up to 63 + kRecheckInPlace - 1 entries)
+    while (rn > 0) {
+        const int k = rn < 64 ? rn : 64;
+        recheck_buffered(k);
+        int64_t rest = 0;
+        if (lane < rn - k) rest = rbuf[k + lane];
+        if (lane < rn - k) rbuf[lane] = rest;
+        rn -= k;
+    }
     if (lane == 0 && rechecked) atomicAdd(&a.q.cnt->n_rechecked, rechecked);
     push_flush(pb, sub_list(a.q), a.q, m, nullptr);
 }

@@ -91,17 +91,32 @@ def _walk_layouts():
             ("integer", Vi, Ci, 4200), ("tiny", V, C[:9], 0)]
 
 
+def _gpu_unset(torch, P, conn, walk):
+    """quad_check on outputs that start as values no kernel writes (memory
+    from torch's allocator may still hold an earlier run's results)."""
+    n = conn.shape[0]
+    v = torch.full((n,), 0xEE, dtype=torch.uint8, device="cuda")
+    m = torch.full((n,), -7.5e300, dtype=torch.float64, device="cuda")
+    st = hx.hexval_stats_t()
+    opts = hx.make_opts(walk_layers=walk, stream=torch.cuda.current_stream(), stats=st)
+    hx.hexval_quad_check(hx.make_mesh(to_dev(torch, P), to_dev(torch, conn)), opts, v, m)
+    torch.cuda.synchronize()
+    v, m = v.cpu().numpy(), m.cpu().numpy()
+    assert not np.any(v == 0xEE) and not np.any(m == -7.5e300), f"walk {walk}: outputs not written"
+    return v, m, st.as_dict()
+
+
 def test_quad_row_walk_equals_plain_tiles_and_oracle():
     # each lane keeps the shared edge of the quads stacked in rows; any
     # connectivity gives the plain pass's results bit for bit
     torch = torch_cuda()
     for label, V, C, stride in _walk_layouts():
         C = np.ascontiguousarray(C.astype(np.int32))
-        bv, bm, bst = _gpu(torch, V, C, walk_layers=-1)
+        bv, bm, bst = _gpu_unset(torch, V, C, -1)
         assert bst["walk_layers"] == 0
         _compare(bv, bm, V, C, label=f"{label} plain")
         for walk in (16, 3, 64):
-            v, m, st = _gpu(torch, V, C, walk_layers=walk)
+            v, m, st = _gpu_unset(torch, V, C, walk)
             _say(f"quads {label} walk {walk}: stride {st['walk_stride']}, exact {st['n_exact']}")
             assert st["walk_layers"] == (walk if C.shape[0] >= 8 * 4096 else 0)
             if stride is not None and C.shape[0] >= 8 * 4096:

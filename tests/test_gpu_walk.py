@@ -20,11 +20,33 @@ def lattice(jitter=0.05, seed=11):
     return synth.warped_lattice(NX, NY, NZ, seed=seed, jitter_fraction=jitter)
 
 
+# Outputs start as values no kernel writes, so that an element left without a
+# result shows (memory from torch's allocator may still hold an earlier
+# run's outputs).
+V_UNSET, M_UNSET = 0xEE, -7.5e300
+
+
+def unset_outputs(torch, n):
+    return (torch.full((n,), V_UNSET, dtype=torch.uint8, device="cuda"),
+            torch.full((n,), M_UNSET, dtype=torch.float64, device="cuda"))
+
+
+def assert_all_written(v, m, label=""):
+    assert not np.any(v == V_UNSET), f"{label}: {np.count_nonzero(v == V_UNSET)} verdicts not written"
+    assert not np.any(m == M_UNSET), f"{label}: {np.count_nonzero(m == M_UNSET)} min_coeff not written"
+
+
 def run(torch, V, C, walk, precision=hx.FP64, max_depth=6):
-    v, m, st = hx.check(to_dev(torch, V), to_dev(torch, C), precision=precision, max_depth=max_depth,
-                        stats=True, walk_layers=walk)
+    n = C.shape[0]
+    v, m = unset_outputs(torch, n)
+    st = hx.hexval_stats_t()
+    opts = hx.make_opts(precision=precision, max_depth=max_depth, walk_layers=walk,
+                        stream=torch.cuda.current_stream(), stats=st)
+    hx.hexval_check_ex(hx.make_mesh(to_dev(torch, V), to_dev(torch, C)), opts, v, m)
     torch.cuda.synchronize()
-    return v.cpu().numpy(), m.cpu().numpy(), st
+    v, m = v.cpu().numpy(), m.cpu().numpy()
+    assert_all_written(v, m, f"walk {walk} precision {precision}")
+    return v, m, st.as_dict()
 
 
 def check_layout(torch, V, C, label, expect_stride=None, precisions=(hx.FP64, hx.FP32_FILTER)):
@@ -133,13 +155,14 @@ def test_min_jacobian_walk_equals_plain_tiles():
     res = {}
     for walk in (-1, 16):
         n = C.shape[0]
-        lo = torch.empty(n, dtype=torch.float64, device="cuda")
-        hi = torch.empty_like(lo)
-        status = torch.empty(n, dtype=torch.uint8, device="cuda")
+        status, lo = unset_outputs(torch, n)
+        hi = lo.clone()
         opts = hx.make_opts(walk_layers=walk, stream=torch.cuda.current_stream())
         hx.hexval_min_jacobian(hx.make_mesh(pts, conn, n), opts, 1e-3, lo, hi, status)
         torch.cuda.synchronize()
         res[walk] = (lo.cpu().numpy(), hi.cpu().numpy(), status.cpu().numpy())
+        assert_all_written(res[walk][2], res[walk][0], f"min J walk {walk}")
+        assert_all_written(res[walk][2], res[walk][1], f"min J walk {walk}")
     for a, b in zip(res[-1], res[16]):
         assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
     ref = oracle.min_jacobian(V, C, rtol=1e-3, max_depth=6)
@@ -148,15 +171,19 @@ def test_min_jacobian_walk_equals_plain_tiles():
 
 
 def batch_run(torch, meshes, walk, precision=hx.FP64, max_depth=6):
-    vs = [torch.empty(C.shape[0], dtype=torch.uint8, device="cuda") for _, C in meshes]
-    ms = [torch.empty(C.shape[0], dtype=torch.float64, device="cuda") for _, C in meshes]
+    outs = [unset_outputs(torch, C.shape[0]) for _, C in meshes]
+    vs = [o[0] for o in outs]
+    ms = [o[1] for o in outs]
     descs = [hx.make_mesh(V, C) for V, C in meshes]
     st = hx.hexval_stats_t()
     opts = hx.make_opts(precision=precision, max_depth=max_depth, walk_layers=walk,
                         stream=torch.cuda.current_stream(), stats=st)
     hx.hexval_check_batched(descs, opts, vs, ms)
     torch.cuda.synchronize()
-    return [v.cpu().numpy() for v in vs], [m.cpu().numpy() for m in ms], st
+    vs, ms = [v.cpu().numpy() for v in vs], [m.cpu().numpy() for m in ms]
+    for k, (v, m) in enumerate(zip(vs, ms)):
+        assert_all_written(v, m, f"batched walk {walk} precision {precision} mesh {k}")
+    return vs, ms, st
 
 
 def mixed_batch():
