@@ -260,6 +260,25 @@ def hexval_last_error():
 
 # ---------------------------------------------------------------- conveniences
 
+def _unset(shape, dtype, device):
+    """An output tensor of the allocating helpers below: it starts as a value
+    no kernel writes (0xEE for uint8, NaN for float64), so that an element the
+    library left without a result shows instead of whatever the memory held
+    (torch's allocator hands back earlier tensors' memory)."""
+    import torch
+    shape = (shape,) if isinstance(shape, int) else tuple(shape)
+    return torch.full(shape, 0xEE if dtype == torch.uint8 else float("nan"), dtype=dtype, device=device)
+
+
+def _after_fill(stream, device):
+    """The fills run on torch's current stream: wait for them when the call
+    runs on another stream."""
+    import torch
+    cur = torch.cuda.current_stream(device)
+    if stream is not None and _stream_handle(stream) != _stream_handle(cur):
+        cur.synchronize()
+
+
 def check(points, connectivity=None, precision=FP64, max_depth=6, validate_indices=False,
           stream=None, stats=False, block_threads=0, grid_blocks=0, queue_capacity=0,
           want_min=True, walk_layers=0):
@@ -270,8 +289,9 @@ def check(points, connectivity=None, precision=FP64, max_depth=6, validate_indic
     [n] or None, stats dict or None)."""
     import torch
     n = connectivity.shape[0] if connectivity is not None else points.shape[0]
-    verdicts = torch.empty(n, dtype=torch.uint8, device=points.device)
-    mins = torch.empty(n, dtype=torch.float64, device=points.device) if want_min else None
+    verdicts = _unset(n, torch.uint8, points.device)
+    mins = _unset(n, torch.float64, points.device) if want_min else None
+    _after_fill(stream, points.device)
     st = hexval_stats_t()
     st.timing = 1 if stats else 0
     if stream is None:
@@ -285,7 +305,8 @@ def check(points, connectivity=None, precision=FP64, max_depth=6, validate_indic
 def coefficients(points, connectivity=None, stream=None):
     import torch
     n = connectivity.shape[0] if connectivity is not None else points.shape[0]
-    out = torch.empty((n, 27), dtype=torch.float64, device=points.device)
+    out = _unset((n, 27), torch.float64, points.device)
+    _after_fill(stream, points.device)
     if stream is None:
         stream = torch.cuda.current_stream(points.device)
     hexval_coefficients(make_mesh(points, connectivity, n), stream, out)
@@ -298,9 +319,10 @@ def min_jacobian(points, connectivity=None, rtol=1e-3, max_depth=6, validate_ind
     stats dict or None) as torch tensors on points' device."""
     import torch
     n = connectivity.shape[0] if connectivity is not None else points.shape[0]
-    lo = torch.empty(n, dtype=torch.float64, device=points.device)
-    hi = torch.empty(n, dtype=torch.float64, device=points.device)
-    status = torch.empty(n, dtype=torch.uint8, device=points.device)
+    lo = _unset(n, torch.float64, points.device)
+    hi = _unset(n, torch.float64, points.device)
+    status = _unset(n, torch.uint8, points.device)
+    _after_fill(stream, points.device)
     st = hexval_stats_t()
     st.timing = 1 if stats else 0
     if stream is None:
@@ -316,8 +338,9 @@ def corner_test(points, connectivity=None, validate_indices=False, stream=None, 
     quality float64 or None, stats dict or None) on points' device."""
     import torch
     n = connectivity.shape[0] if connectivity is not None else points.shape[0]
-    test1 = torch.empty(n, dtype=torch.uint8, device=points.device)
-    quality = torch.empty(n, dtype=torch.float64, device=points.device) if want_quality else None
+    test1 = _unset(n, torch.uint8, points.device)
+    quality = _unset(n, torch.float64, points.device) if want_quality else None
+    _after_fill(stream, points.device)
     st = hexval_stats_t()
     st.timing = 1 if stats else 0
     if stream is None:
@@ -334,8 +357,9 @@ def quad_check(points, connectivity=None, validate_indices=False, stream=None, s
     stats dict or None)."""
     import torch
     n = connectivity.shape[0] if connectivity is not None else points.shape[0]
-    verdicts = torch.empty(n, dtype=torch.uint8, device=points.device)
-    min_j = torch.empty(n, dtype=torch.float64, device=points.device) if want_min else None
+    verdicts = _unset(n, torch.uint8, points.device)
+    min_j = _unset(n, torch.float64, points.device) if want_min else None
+    _after_fill(stream, points.device)
     st = hexval_stats_t()
     st.timing = 1 if stats else 0
     if stream is None:
