@@ -402,13 +402,15 @@ static int exact_tier(Workspace& w, const double* pts, uint8_t* v, uint8_t* hv, 
 // ---------------------------------------------------------------- autotuner
 // Launch shape of the first-pass kernel: threads per block (= elements per
 // tile), a persistent grid of k blocks per CU (4, 8, 16 or 32) taking tiles
-// at run time and, for a single mesh with trusted connectivity in FP64, the
-// column walk's layers per tile (0: plain tiles, or kWalkLayers).  Picked by
-// timing every candidate twice on the call's own input (the better time
-// counts), cached per (device architecture, precision, gather mode, batched,
-// log2 size bucket) and optionally persisted in the file named by
-// HEXVAL_TUNE_CACHE.  The per-element arithmetic never depends on the launch
-// shape.
+// at run time and, where the input may walk (a single mesh with trusted
+// connectivity, or an FP64 batch of them), the column walk's layers per tile
+// (0: plain tiles, or kWalkLayers).  Picked by timing every candidate twice
+// on the call's own input (the better time counts; a walking candidate's
+// time includes its stride search), cached per (device architecture,
+// precision, gather mode, batched, log2 size bucket) and optionally persisted
+// in the file named by HEXVAL_TUNE_CACHE (keys of version v4: earlier files
+// recorded no walk choice for batches).  The per-element arithmetic never
+// depends on the launch shape.
 
 struct TuneChoice {
     int block = 256;
@@ -425,7 +427,7 @@ static std::string tune_key(const char* arch, int precision, int gather, bool ba
     int bucket = 0;
     while ((1ll << (bucket + 1)) <= total) ++bucket;
     char buf[128];
-    snprintf(buf, sizeof buf, "v3/%s/p%d/g%d/b%d/n%d", arch, precision, gather, batched ? 1 : 0, bucket);
+    snprintf(buf, sizeof buf, "v4/%s/p%d/g%d/b%d/n%d", arch, precision, gather, batched ? 1 : 0, bucket);
     return buf;
 }
 
