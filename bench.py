@@ -580,7 +580,10 @@ def main():
                      "avg_launch_ms": float(first.mean()),
                      "valu": {"achieved": valu_ops, "peak": VALU_PEAK_OPS, "unit": "FP64 lane-ops/s",
                               "frac": valu_ops / VALU_PEAK_OPS, "ops_per_hex": VALU_OPS_PER_HEX},
-                     "frac_of_measured_read_ceiling": achieved / ceilings["hbm_read_GBps"]},
+                     "frac_of_measured_read_ceiling": achieved / ceilings["hbm_read_GBps"],
+                     # the whole call (first pass, stride search, subdivision, fold, counters
+                     # read back) against the same bytes: what the step's wall time reaches
+                     "frac_per_call": alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "machine_ceilings": ceilings,
         "verdicts": {"invalid": hist[0], "valid": hist[1], "undecided": hist[2],
                      "bad_input": hist[3]},
