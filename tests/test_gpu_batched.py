@@ -23,9 +23,11 @@ def _alone(torch, V, C, **kw):
 
 
 def _batched(torch, meshes, precision=hx.FP64, stats=None, **kw):
-    vs = [torch.empty(C.shape[0] if C is not None else V.shape[0], dtype=torch.uint8, device="cuda")
+    # outputs start as values no kernel writes (0xEE, NaN): an element left
+    # without a result cannot pass on an earlier run's values in reused memory
+    vs = [torch.full((C.shape[0] if C is not None else V.shape[0],), 0xEE, dtype=torch.uint8, device="cuda")
           for V, C in meshes]
-    ms = [torch.empty(v.shape[0], dtype=torch.float64, device="cuda") for v in vs]
+    ms = [torch.full((v.shape[0],), float("nan"), dtype=torch.float64, device="cuda") for v in vs]
     descs = [hx.make_mesh(V, C) for V, C in meshes]
     opts = hx.make_opts(precision=precision, stream=torch.cuda.current_stream(), stats=stats, **kw)
     hx.hexval_check_batched(descs, opts, vs, ms)
