@@ -768,9 +768,10 @@ struct CarrySlots {
 
 // Vertex loads of one element with the carried face: corners 4..7 always,
 // corners 0..3 only when this lane's slots do not hold them.  Returns
-// whether they do.  The 4 id comparisons are combined without short
-// circuit: as a chain of branches each slot read waited for the one before,
-// and the vertex loads went out only after the last.
+// whether they do.  The 4 ids are compared as two 64-bit pairs, after the
+// loads have gone out: as a chain of short-circuit branches each slot read
+// waited for the one before, and the vertex loads went out only after the
+// last.
 __device__ __forceinline__ bool carry_issue(const double* points, const int idx[8], const CarrySlots& cs, V3 p[8])
 {
     const int l = threadIdx.x;
@@ -779,8 +780,9 @@ __device__ __forceinline__ bool carry_issue(const double* points, const int idx[
         const auto* v = global(points) + 3 * (int64_t)idx[k];
         p[k] = {v[0], v[1], v[2]};
     }
-    const bool hit = (idx[0] == cs.id[l]) & (idx[1] == cs.id[256 + l]) & (idx[2] == cs.id[512 + l]) &
-                     (idx[3] == cs.id[768 + l]);
+    auto pair = [](int lo, int hi) { return (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32); };
+    const bool hit = (pair(idx[0], idx[1]) == pair(cs.id[l], cs.id[256 + l])) &
+                     (pair(idx[2], idx[3]) == pair(cs.id[512 + l], cs.id[768 + l]));
     if (!hit) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
