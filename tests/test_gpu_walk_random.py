@@ -3,7 +3,8 @@ equal to the plain-tile pass bit for bit, with outputs that start as values
 no kernel writes (HIP path through the C ABI).  The layouts mix stacked,
 jittered, cut, partly permuted and row-replaced meshes, near-degenerate
 hexes appended after a lattice, depth caps 0, 3 and 6, single meshes in FP64
-and with the FP32 filter, FP64 batches, and quadrangle meshes."""
+and with the FP32 filter (also without the min output), FP64 batches, and
+quadrangle meshes."""
 import numpy as np
 import pytest
 
@@ -71,6 +72,16 @@ def _single(torch, Vd, Cd, walk, prec, cap):
     return out, st
 
 
+def _verdicts_only(torch, Vd, Cd, walk, prec, cap):
+    v, _ = _unset(torch, Cd.shape[0])
+    opts = hx.make_opts(precision=prec, max_depth=cap, walk_layers=walk, stream=torch.cuda.current_stream())
+    hx.hexval_check_ex(hx.make_mesh(Vd, Cd), opts, v, None)
+    torch.cuda.synchronize()
+    v = v.cpu().numpy()
+    assert not np.any(v == V_UNSET), f"walk {walk} precision {prec}, no min output: verdicts not written"
+    return v
+
+
 def _batch(torch, meshes, walk, cap):
     outs = [_unset(torch, c.shape[0]) for _, c in meshes]
     opts = hx.make_opts(max_depth=cap, walk_layers=walk, stream=torch.cuda.current_stream())
@@ -108,6 +119,9 @@ def test_random_layouts_walk_equals_plain_tiles():
                 _same(base, out, f"case {case} precision {prec} walk {walk} cap {cap}")
                 assert st.n_recheck == bst.n_recheck
                 walked += st.walk_stride > 0
+            if case % 5 == 0:
+                assert np.array_equal(_verdicts_only(torch, Vd, Cd, 16, prec, cap), base[0]), \
+                    f"case {case} precision {prec}: verdicts without the min output differ"
         if case % 4 == 0:
             meshes = [(Vd, Cd)]
             for _ in range(int(rng.integers(1, 5))):
