@@ -560,7 +560,11 @@ __device__ __forceinline__ void batch_prefetch_loop(const MeshDev* meshes, const
         gather8(m.points, idx, p);     // every lane holds a valid row
         int mi_n = mi;
         MeshDev mn = m;
-        if (tn >= 0) mn = mesh_of(tn, mi_n);
+        // the tables only when the next tile leaves this mesh (a tile's
+        // successor is usually a later tile of the same mesh): the next rows
+        // then go out without waiting for scalar loads
+        const int64_t rel = tn - m.tile_begin;
+        if (tn >= 0 && !(rel >= 0 && rel * (int64_t)blockDim.x < m.n)) mn = mesh_of(tn, mi_n);
         wait_lds();                    // the slots are free: every lane has read its row
         prefetch(tn >= 0 ? tn : t, mn);
         wait_loads();                  // vertices and the next rows have landed
