@@ -29,9 +29,11 @@
  *     BAD_INPUT.  Computed in FP64 it is within 256 u M^ of the exact
  *     minimum (u = 2^-53, M^ = 6 S_xi S_eta S_zeta, S_d the largest |component|
  *     of the element's four edge vectors along direction d); under
- *     HEXVAL_FP32_FILTER an element the FP32 pass decides returns the FP32
- *     minimum widened to double, within 256 u32 M^ (u32 = 2^-24), and an
- *     element rechecked in FP64 returns the FP64 value.
+ *     HEXVAL_FP32_FILTER an element the FP32 pass decides, or sends to
+ *     subdivision itself (every corner value above twice its FP32 bound and
+ *     some coefficient certainly negative), returns the FP32 minimum widened
+ *     to double, within 256 u32 M^ (u32 = 2^-24), and an element rechecked
+ *     in FP64 returns the FP64 value.
  *
  * Conventions for every entry point:
  *   - array pointers named "device" are device pointers (hipMalloc'd memory or
@@ -82,8 +84,9 @@ enum {
                                coefficient; elements it cannot certify, and every
                                subdivision, are recomputed in FP64.  Verdicts are
                                those of HEXVAL_FP64; min_coeff of an element the
-                               FP32 pass decides is FP32-accurate (within
-                               256 u32 M^, see min_coeff above) */
+                               FP32 pass decides or sends to subdivision is
+                               FP32-accurate (within 256 u32 M^, see min_coeff
+                               above) */
 };
 
 /* A mesh.  points: device, [n_points,3] float64 when connectivity != NULL,

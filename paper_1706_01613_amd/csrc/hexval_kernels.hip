@@ -191,6 +191,14 @@ struct PushBuf {
     PushBuf pb{(__attribute__((address_space(3))) int64_t*)(push_elem_ + (threadIdx.x >> 6) * kPushBuf), \
                (__attribute__((address_space(3))) int32_t*)(push_mesh_ + (threadIdx.x >> 6) * kPushBuf), 0}
 
+// A second set for kernels that append to two lists (the FP32 filter: its
+// recheck list, and the subdivision list for what filter_subdivides sends).
+#define HX_SUB_PUSH_STORAGE                                          \
+    __shared__ int64_t sub_elem_[4 * kPushBuf];                      \
+    __shared__ int32_t sub_mesh_[4 * kPushBuf];                      \
+    PushBuf sb{(__attribute__((address_space(3))) int64_t*)(sub_elem_ + (threadIdx.x >> 6) * kPushBuf), \
+               (__attribute__((address_space(3))) int32_t*)(sub_mesh_ + (threadIdx.x >> 6) * kPushBuf), 0}
+
 // A list that buffered entries are appended to: the subdivision list, or
 // the FP32 filter's FP64 recheck list.
 struct ListRef {
@@ -999,42 +1007,50 @@ __global__ __launch_bounds__(256) void k_top_f64_list(TopArgs a)
 // FP32 decisions for one element per lane.  Elements that need the FP64 pass
 // go to the recheck list through the wave's buffer (as finish_element sends
 // elements to subdivision), without a block barrier per tile.
+// Elements filter_subdivides clears (with a depth cap above 0) skip the
+// recheck: they go to the subdivision list through a second buffer, sb, with
+// their FP32 minimum as min_coeff, as the FP32-decided elements.
 __device__ void filter_finish(const MeshDev& m, int mesh_idx, int64_t e, bool active, const V3 p[8], bool bad,
-                              const QueueDev& q, PushBuf& pb, const MeshDev* meshes)
+                              const QueueDev& q, int max_depth, PushBuf& pb, PushBuf& sb, const MeshDev* meshes)
 {
     int st = -1;
+    bool sub = false;
     float mn = 0.0f;
     if (active) {
         if (!bad) {
             const LeanT<float> r = element_lean_t<float>(p, false);
             st = filter_state(r);
+            sub = st < 0 && max_depth > 0 && filter_subdivides(r);
             mn = r.min27;
         }
     }
-    const bool recheck = active && !bad && st < 0;
+    const bool recheck = active && !bad && st < 0 && !sub;
     const uint8_t v = bad ? 3 : (uint8_t)st;
     push_entry(pb, recheck_list(q), q, m, meshes, recheck, e, mesh_idx);
+    push_entry(sb, sub_list(q), q, m, meshes, sub, e, mesh_idx);
     if (active && !recheck) {
-        *global(m.verdict + e) = v;
+        if (!sub) *global(m.verdict + e) = v;   // listed elements: at push_flush
         if (m.min_coeff) *global(m.min_coeff + e) = bad ? __builtin_nan("") : (double)mn;
     }
     if (pb.n > kPushBuf - 64) push_flush(pb, recheck_list(q), q, m, meshes);
+    if (sb.n > kPushBuf - 64) push_flush(sb, sub_list(q), q, m, meshes);
 }
 
 template <int G>
 __device__ void filter_element(const MeshDev& m, int mesh_idx, int64_t e, bool active, const QueueDev& q,
-                               PushBuf& pb, const MeshDev* meshes)
+                               int max_depth, PushBuf& pb, PushBuf& sb, const MeshDev* meshes)
 {
     V3 p[8];
     bool bad = false;
     if (active) load_points_t<G>(m, e, p, bad);
-    filter_finish(m, mesh_idx, e, active, p, bad, q, pb, meshes);
+    filter_finish(m, mesh_idx, e, active, p, bad, q, max_depth, pb, sb, meshes);
 }
 
 template <bool BATCHED, int G>
 __global__ __launch_bounds__(256) void k_filter_f32_range(TopArgs a)
 {
     HX_PUSH_STORAGE;
+    HX_SUB_PUSH_STORAGE;
     TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
     for (int64_t t = ts.next_tile(); t >= 0; t = ts.next_tile()) {
         MeshDev m;
@@ -1049,9 +1065,10 @@ __global__ __launch_bounds__(256) void k_filter_f32_range(TopArgs a)
             m = a.mesh;
             e = t * (int64_t)blockDim.x + threadIdx.x;
         }
-        filter_element<G>(m, mi, e, e < m.n, a.q, pb, BATCHED ? a.meshes : nullptr);
+        filter_element<G>(m, mi, e, e < m.n, a.q, a.max_depth, pb, sb, BATCHED ? a.meshes : nullptr);
     }
     push_flush(pb, recheck_list(a.q), a.q, a.mesh, BATCHED ? a.meshes : nullptr);
+    push_flush(sb, sub_list(a.q), a.q, a.mesh, BATCHED ? a.meshes : nullptr);
 }
 
 // k_filter_f32_range for a single mesh with trusted connectivity, through
@@ -1060,15 +1077,17 @@ __global__ __launch_bounds__(256) void k_filter_f32_conn(TopArgs a)
 {
     __shared__ int4 stage[2 * 256];
     HX_PUSH_STORAGE;
+    HX_SUB_PUSH_STORAGE;
     const MeshDev& m = a.mesh;
     TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
     conn_prefetch_loop<8>(m.conn, m.n, ts, stage, [&](int64_t e, bool active, const int* idx) {
         V3 p[8];
         gather8(m.points, idx, p);
         wait_loads();
-        filter_finish(m, 0, e, active, p, false, a.q, pb, nullptr);
+        filter_finish(m, 0, e, active, p, false, a.q, a.max_depth, pb, sb, nullptr);
     });
     push_flush(pb, recheck_list(a.q), a.q, m, nullptr);
+    push_flush(sb, sub_list(a.q), a.q, m, nullptr);
 }
 
 // k_filter_f32_conn with the column walk, and the FP64 recheck in the same
@@ -1130,17 +1149,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         wait_loads();
         carry_finish(idx, hit, cs, p);
         int st = -1;
+        bool sub = false;
         float mn = 0.0f;
         if (active) {
             const LeanT<float> r = element_lean_t<float>(p, false);
             st = filter_state(r);
+            sub = st < 0 && a.max_depth > 0 && filter_subdivides(r);
             mn = r.min27;
         }
-        const bool recheck = active && st < 0;
+        // what filter_subdivides clears goes to subdivision without the recheck
+        push_entry(pb, sub_list(a.q), a.q, m, nullptr, sub, e, 0);
+        const bool recheck = active && st < 0 && !sub;
         if (active && !recheck) {
-            *global(m.verdict + e) = (uint8_t)st;
+            if (!sub) *global(m.verdict + e) = (uint8_t)st;   // listed elements: at push_flush
             if (m.min_coeff) *global(m.min_coeff + e) = (double)mn;
         }
+        if (pb.n > kPushBuf - 64) push_flush(pb, sub_list(a.q), a.q, m, nullptr);
         const uint64_t rm = ballot(recheck);
         const int nr = __popcll(rm);
         if (nr >= kRecheckInPlace) {
@@ -1172,12 +1196,14 @@ __global__ __launch_bounds__(256) void k_filter_f32_batch_conn(TopArgs a)
 {
     __shared__ int4 stage[2 * 256];
     HX_PUSH_STORAGE;
+    HX_SUB_PUSH_STORAGE;
     TileSched ts(a.n_tiles, a.xcds, a.q.cnt);
     batch_prefetch_loop(a.meshes, a.tile_mesh, ts, stage,
                         [&](const MeshDev& m, int mi, int64_t e, bool active, const V3* p) {
-        filter_finish(m, mi, e, active, p, false, a.q, pb, a.meshes);
+        filter_finish(m, mi, e, active, p, false, a.q, a.max_depth, pb, sb, a.meshes);
     });
     push_flush(pb, recheck_list(a.q), a.q, a.mesh, a.meshes);
+    push_flush(sb, sub_list(a.q), a.q, a.mesh, a.meshes);
 }
 
 // ------------------------------------------------------------ subdivision

@@ -507,6 +507,22 @@ HEXVAL_HD int filter_state(const LeanT<float>& r)
     return -1;
 }
 
+// An element the FP32 pass may send to subdivision itself, without the FP64
+// recheck: every corner value above twice its FP32 bound and the Bezier
+// minimum at or below minus its bound.  Then the FP64 values (within
+// kTauValue and kTauCoeff u64 M^ of the exact ones, and those within the
+// FP32 bounds of the FP32 values) keep the corner values above their FP64
+// bound and the Bezier minimum below its own, so the FP64 evaluation would
+// subdivide the element too (lean_state with max_depth > 0).  Subdivision
+// recomputes its coefficients in FP64, so its verdict is the same.
+HEXVAL_HD bool filter_subdivides(const LeanT<float>& r)
+{
+    if (!r.certified_range) return false;
+    const float tv = kTauValue * kU32 * r.scale;
+    const float tb = kTauCoeff * kU32 * r.scale;
+    return r.m20 > 2.0f * tv && r.mb <= -tb;
+}
+
 HEXVAL_HD int lean_state(const LeanResult& r, int max_depth)
 {
     if (!r.certified_range) return kTopExact;

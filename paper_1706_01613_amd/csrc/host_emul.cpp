@@ -217,6 +217,21 @@ void hexval_emul_lean(const double* pts, const int32_t* conn, int64_t n, int pre
     }
 }
 
+// Per element: 1 where the FP32 filter sends the element to subdivision
+// itself (filter_subdivides), else 0; and the FP64 pass's state at depth
+// cap 6 (0..4 as hexval_emul_values).
+void hexval_emul_filter_subdivides(const double* pts, const int32_t* conn, int64_t n, int32_t* sub,
+                                   int32_t* state64)
+{
+    for (int64_t e = 0; e < n; ++e) {
+        V3 p[8];
+        double raw[24];
+        gather(pts, conn, e, p, raw);
+        sub[e] = filter_subdivides(element_lean_t<float>(p, false)) ? 1 : 0;
+        state64[e] = lean_state(element_lean(p, false), 6);
+    }
+}
+
 // Bound constants of the kernels: {tau_value, tau_coeff, tau_level, u64, u32}.
 // The kernels' outward rounding of min-J bounds, element-wise.
 void hexval_emul_next(const double* x, int64_t n, double* down, double* up)

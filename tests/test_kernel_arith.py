@@ -199,3 +199,36 @@ def test_outward_rounding_is_nextafter(emul):
     assert np.array_equal(down.view(np.int64)[~np.isnan(x)], want_down.view(np.int64)[~np.isnan(x)])
     assert np.array_equal(up.view(np.int64)[~np.isnan(x)], want_up.view(np.int64)[~np.isnan(x)])
     assert np.isnan(down[np.isnan(x)]).all() and np.isnan(up[np.isnan(x)]).all()
+
+
+def test_fp32_filter_sends_to_subdivision_only_what_fp64_subdivides(emul):
+    """The FP32 filter lists an element for subdivision itself, without the
+    FP64 recheck, only when its corner values are above twice their FP32
+    bound and its Bezier minimum at or below minus its bound.  Every such
+    element must be one the FP64 pass subdivides too, and one the oracle does
+    not decide at the root (Section 6: some coefficient negative, every
+    corner positive)."""
+    emul.hexval_emul_filter_subdivides.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                                   ctypes.c_void_p, ctypes.c_void_p]
+    X = np.concatenate([synth.independent_hexes(60000, seed=3),
+                        synth.independent_hexes(60000, noise=0.6, seed=4),
+                        synth.near_degenerate_hexes(10000, seed=5),
+                        (synth.independent_hexes(20000, noise=0.5, seed=6)
+                         * 10.0 ** np.random.default_rng(7).uniform(-3, 3, size=(20000, 1, 1))),
+                        synth.independent_hexes(20000, noise=0.5, seed=8) + 1000.0])
+    X = np.ascontiguousarray(X)
+    n = X.shape[0]
+    sub = np.empty(n, np.int32)
+    st64 = np.empty(n, np.int32)
+    emul.hexval_emul_filter_subdivides(X.ctypes.data, None, n, sub.ctypes.data, st64.ctypes.data)
+    flagged = sub == 1
+    assert flagged.sum() > 1000
+    assert (st64[flagged] == 3).all()            # kTopSubdivide in the FP64 pass
+    idx = np.nonzero(flagged)[0][::7]
+    r = oracle.check(X[idx], details=True)
+    b = oracle.coefficients(X[idx])
+    assert (b[:, :8] > 0).all()                  # every corner value positive
+    assert (b[:, 8:].min(axis=1) < 0).all()      # and some coefficient negative
+    # the oracle subdivides them, or (testing the 12 edge-midpoint values at
+    # the root, which the kernels leave to level 1) finds one non-positive
+    assert ((r["level"] >= 1) | (r["verdict"] == oracle.INVALID)).all()
